@@ -1,0 +1,108 @@
+"""Python access to the plain CPU oracle (``sieve_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` use this module.  The GPU library never imports
+it, and it imports nothing from the GPU package.
+
+The oracle computes the odd-only sieve table of Definition 1 (Section 1.3) for the
+interval of Section 1.2.1, u = f*2^(l+1)+1 .. v = (f+n)*2^(l+1), by marking every
+odd multiple m*p (m >= 3) of every odd prime p <= B.  See the C file's header.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sieve_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain -O2, no vector intrinsics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        lib.oracle_sieve.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint64, u32p, u32p]
+        lib.oracle_sieve.restype = ctypes.c_int
+        lib.oracle_odd_primes.argtypes = [ctypes.c_uint64, ctypes.POINTER(u32p)]
+        lib.oracle_odd_primes.restype = ctypes.c_long
+        lib.oracle_lemma1_offset.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
+        lib.oracle_lemma1_offset.restype = ctypes.c_uint32
+        lib.oracle_lemma2_skip.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        lib.oracle_lemma2_skip.restype = ctypes.c_uint64
+        lib.oracle_count_total.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.c_uint64]
+        lib.oracle_count_total.restype = ctypes.c_longlong
+        libc = ctypes.CDLL(None)
+        libc.free.argtypes = [ctypes.c_void_p]
+        lib._free = libc.free
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def sieve(l, f, n, B):
+    """Definition 1: returns (S as uint32 words, counts per 2^l-bit segment)."""
+    lib = _load()
+    nwords = (n << l) // 32
+    S = np.zeros(max(nwords, 1), dtype=np.uint32)
+    c = np.zeros(max(n, 1), dtype=np.uint32)
+    rc = lib.oracle_sieve(l, f, n, B,
+                          S.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                          c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    if rc != 0:
+        raise OracleError("oracle_sieve(l=%d, f=%d, n=%d, B=%d) -> %d" % (l, f, n, B, rc))
+    return S[:nwords], c[:n]
+
+
+def odd_primes(B):
+    """Odd primes 3 <= p <= B (plain sieve of Eratosthenes, Section 1.1)."""
+    lib = _load()
+    ptr = ctypes.POINTER(ctypes.c_uint32)()
+    cnt = lib.oracle_odd_primes(B, ctypes.byref(ptr))
+    if cnt < 0:
+        raise OracleError("out of memory")
+    out = np.ctypeslib.as_array(ptr, shape=(max(cnt, 1),))[:cnt].copy()
+    lib._free(ptr)
+    return out
+
+
+def lemma1_offset(p, f, l):
+    """Lemma 1 (Section 2.1): unique 0 <= q < p with p | 2(f*2^l + q) + 1."""
+    return _load().oracle_lemma1_offset(p, f, l)
+
+
+def lemma2_skip(p, q, l):
+    """Lemma 2 (Section 2.2): number of segments skipped after a hit at offset q."""
+    return _load().oracle_lemma2_skip(p, q, l)
+
+
+def count_total(l, f, n, B):
+    """Sum of the per-segment zero-bit counts of Definition 1's table."""
+    r = _load().oracle_count_total(l, f, n, B)
+    if r < 0:
+        raise OracleError("oracle_count_total failed")
+    return r
+
+
+def interval(l, f, n):
+    """Section 1.2.1: u = f*2^(l+1)+1, v = (f+n)*2^(l+1)."""
+    return f * (1 << (l + 1)) + 1, (f + n) * (1 << (l + 1))

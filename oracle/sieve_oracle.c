@@ -1,0 +1,149 @@
+/*
+ * sieve_oracle.c -- plain, slow, single-threaded CPU reference for the odd-only
+ * sieve table of Jarai & Vatai, "Cache optimized linear sieve" (2011).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity oracle for the GPU library.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.  It shares no code, header, table or constant with the GPU path,
+ * and the GPU path never calls it.
+ *
+ * What it computes (Section 1.2.1 "Input and output" and Definition 1 "Sieve
+ * table, Segments" of Section 1.3):
+ *   parameters l, f, n give the interval u = f*2^(l+1) + 1 .. v = (f+n)*2^(l+1);
+ *   the table S has n*2^l bits, bit j stands for the odd number N_j = u + 2j;
+ *   S_j = 1 (composite) iff N_j == 1, or N_j has an odd prime divisor p with
+ *   3 <= p <= B and p < N_j.  With B >= isqrt(v) this is "S_j = 0 iff N_j is
+ *   prime" (Section 1.4: primes up to sqrt(v) suffice).
+ *   counts[t] = number of zero bits in segment t (bits t*2^l .. (t+1)*2^l - 1).
+ *
+ * The method reaches exactly this table faster; the oracle is the definition
+ * written out: for every odd prime p <= B it sets the bit of every odd multiple
+ * m*p with m >= 3 that lies in [u, v] (Section 1.1: mark the multiples of each
+ * prime; Section 1.3: in the odd-only table consecutive odd multiples of p are p
+ * bits apart).  No segmenting, no wheel, no buckets: those are the method's
+ * speed-ups, not its result.  Bit j lives in 32-bit word j/32 at bit position
+ * j%32 (least significant bit first).
+ *
+ * The number 1 (only present when f == 0) is set to 1 ("not prime"); the paper
+ * does not say, and 1 is not a prime.
+ *
+ * Parity status: pinned (tests/test_oracle_pins.py: trial division on small
+ * ranges, Miller-Rabin on sampled bits, known values of pi(x), Lemma 1 by
+ * brute force).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+enum { OR_OK = 0, OR_E_ARG = -1, OR_E_RANGE = -2, OR_E_BOUND = -3, OR_E_NOMEM = -4 };
+
+/* Odd primes 3 <= p <= B by the plain sieve of Eratosthenes (Section 1.1) over
+ * the odd numbers 1..B; entry k of the byte array stands for 2k+1.  Returns the
+ * number of primes written to *out (malloc'ed, caller frees) or -1. */
+long oracle_odd_primes(uint64_t B, uint32_t **out)
+{
+    *out = NULL;
+    if (B < 3) { *out = (uint32_t *)malloc(4); return *out ? 0 : -1; }
+    uint64_t K = (B - 1) / 2 + 1;            /* odd numbers 1,3,...,<=B */
+    unsigned char *comp = (unsigned char *)calloc(K, 1);
+    if (!comp) return -1;
+    for (uint64_t k = 1; k < K; ++k) {
+        if (comp[k]) continue;
+        uint64_t p = 2 * k + 1;
+        if (p * p > B) break;
+        for (uint64_t m = (p * p - 1) / 2; m < K; m += p) comp[m] = 1;
+    }
+    long cnt = 0;
+    for (uint64_t k = 1; k < K; ++k) cnt += !comp[k];
+    uint32_t *pr = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(cnt > 0 ? cnt : 1));
+    if (!pr) { free(comp); return -1; }
+    long w = 0;
+    for (uint64_t k = 1; k < K; ++k) if (!comp[k]) pr[w++] = (uint32_t)(2 * k + 1);
+    free(comp);
+    *out = pr;
+    return cnt;
+}
+
+/* Validate (l, f, n, B) and return u, v, F = f*2^l, NB = n*2^l. */
+static int oracle_interval(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                           uint64_t *F, uint64_t *NB, uint64_t *u, uint64_t *v)
+{
+    if (l < 5 || l > 30 || n == 0) return OR_E_ARG;
+    if (B < 3 || B >= ((uint64_t)1 << 32)) return OR_E_BOUND;
+    u128 FF = (u128)f << l, NN = (u128)n << l;
+    u128 vv = 2 * (FF + NN);
+    if (vv >= ((u128)1 << 64)) return OR_E_RANGE;
+    *F = (uint64_t)FF; *NB = (uint64_t)NN; *u = 2 * *F + 1; *v = (uint64_t)vv;
+    return OR_OK;
+}
+
+/* Definition 1 written out.  S must hold n*2^l/32 words, counts n words. */
+int oracle_sieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                 uint32_t *S, uint32_t *counts)
+{
+    uint64_t F, NB, u, v;
+    int rc = oracle_interval(l, f, n, B, &F, &NB, &u, &v);
+    if (rc) return rc;
+    memset(S, 0, (size_t)(NB / 32) * 4);
+    uint32_t *P = NULL;
+    long np = oracle_odd_primes(B, &P);
+    if (np < 0) return OR_E_NOMEM;
+    for (long i = 0; i < np; ++i) {
+        uint64_t p = P[i];
+        /* smallest odd cofactor m >= 3 with m*p >= u */
+        u128 m = ((u128)u + p - 1) / p;
+        if (m < 3) m = 3;
+        if ((m & 1) == 0) m += 1;
+        u128 N = m * p;
+        if (N > v) continue;
+        uint64_t j = (uint64_t)((N - u) / 2);
+        for (; j < NB; j += p) S[j >> 5] |= 1u << (j & 31);
+    }
+    free(P);
+    if (u == 1) S[0] |= 1u;                  /* the number 1 is not prime */
+    uint64_t wps = ((uint64_t)1 << l) / 32;  /* words per segment */
+    for (uint64_t t = 0; t < n; ++t) {
+        uint64_t ones = 0;
+        for (uint64_t w = t * wps; w < (t + 1) * wps; ++w)
+            ones += (uint64_t)__builtin_popcount(S[w]);
+        counts[t] = (uint32_t)(((uint64_t)1 << l) - ones);
+    }
+    return OR_OK;
+}
+
+/* Lemma 1 (Section 2.1), in the paper's own steps: with r = f*2^(l+1) mod p the
+ * unique 0 <= q < p with p | 2(f*2^l + q) + 1 is (p-r-1)/2 for even r and
+ * (2p-r-1)/2 for odd r.  Here f may be any 64-bit value and l <= 63. */
+uint32_t oracle_lemma1_offset(uint32_t p, uint64_t f, uint32_t l)
+{
+    u128 x = (u128)f << (l + 1);
+    uint64_t r = (uint64_t)(x % p);
+    if ((r & 1) == 0) return (uint32_t)((p - r - 1) / 2);
+    return (uint32_t)((2 * (uint64_t)p - r - 1) / 2);
+}
+
+/* Lemma 2 (Section 2.2): for k*2^l <= p < (k+1)*2^l, a hit at offset q of
+ * segment t is followed by a hit in segment t + k or t + k + 1.  Returns the
+ * segment skip floor((q + p) / 2^l) for a hit at offset q. */
+uint64_t oracle_lemma2_skip(uint32_t p, uint32_t q, uint32_t l)
+{
+    return ((uint64_t)q + p) >> l;
+}
+
+/* Reference batch helper: n31 = number of 2^l-bit segments; same as
+ * oracle_sieve but returns only the count total (no table kept) for a sample
+ * used by the CPU baseline timing.  Returns -1 on error. */
+long long oracle_count_total(uint32_t l, uint64_t f, uint64_t n, uint64_t B)
+{
+    uint64_t NBw = ((uint64_t)n << l) / 32;
+    uint32_t *S = (uint32_t *)malloc((size_t)NBw * 4);
+    uint32_t *c = (uint32_t *)malloc((size_t)n * 4);
+    if (!S || !c) { free(S); free(c); return -1; }
+    int rc = oracle_sieve(l, f, n, B, S, c);
+    long long tot = 0;
+    if (rc == 0) for (uint64_t t = 0; t < n; ++t) tot += c[t];
+    free(S); free(c);
+    return rc == 0 ? tot : -1;
+}

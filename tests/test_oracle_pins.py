@@ -1,0 +1,196 @@
+"""Pins for the CPU oracle: values fixed by mathematics, not by the oracle itself.
+
+* brute-force trial division of every represented number on tiny intervals
+  (Definition 1, Section 1.3, including the partial sieve B < isqrt(v));
+* published values of pi(x) (tests/golden/pi_values.txt);
+* deterministic Miller-Rabin on every bit of mid-size intervals and on random
+  samples of large ones;
+* Lemma 1 (Section 2.1) against the brute-force least offset;
+* Lemma 2 (Section 2.2): the skip after a hit of a prime with k*2^l <= p < (k+1)*2^l
+  is k or k+1 segments.
+"""
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MR_BASES = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+
+
+def is_prime_mr(n):
+    """Deterministic Miller-Rabin for n < 3.3e24 with the first twelve primes as bases."""
+    if n < 2:
+        return False
+    for p in MR_BASES:
+        if n % p == 0:
+            return n == p
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in MR_BASES:
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def smallest_odd_factor(N):
+    d = 3
+    while d * d <= N:
+        if N % d == 0:
+            return d
+        d += 2
+    return N
+
+
+def brute_bits(l, f, n, B):
+    """Definition 1 by trial division: S_j = 1 iff N_j == 1 or N_j has an odd prime
+    divisor p <= B with p < N_j (the least odd factor is that divisor if any is)."""
+    u, _ = O.interval(l, f, n)
+    out = np.zeros(n << l, dtype=np.uint8)
+    for j in range(n << l):
+        N = u + 2 * j
+        if N == 1:
+            out[j] = 1
+            continue
+        q = smallest_odd_factor(N)
+        out[j] = 1 if (q <= B and q < N) else 0
+    return out
+
+
+def bits_of(S):
+    return np.unpackbits(S.view(np.uint8), bitorder="little")
+
+
+def test_brute_force_small_intervals():
+    rng = random.Random(7)
+    cases = [(5, 0, 1, 3), (5, 0, 2, 13), (5, 0, 8, 17), (6, 0, 4, 61), (5, 1, 1, 3),
+             (7, 3, 5, 1000), (10, 0, 4, 64), (8, 64, 3, 11), (9, 17, 2, 3)]
+    for _ in range(40):
+        l = rng.randint(5, 10)
+        f = rng.randint(0, 64)
+        n = rng.randint(1, 8)
+        u, v = O.interval(l, f, n)
+        r = math.isqrt(v)
+        B = rng.choice([r, max(3, r // 3), 3, 5, 13, 17, 31, r + 50])
+        cases.append((l, f, n, B))
+    for (l, f, n, B) in cases:
+        S, c = O.sieve(l, f, n, B)
+        got = bits_of(S)
+        want = brute_bits(l, f, n, B)
+        assert np.array_equal(got, want), (l, f, n, B)
+        seg = (1 << l)
+        for t in range(n):
+            assert c[t] == seg - int(want[t * seg:(t + 1) * seg].sum())
+
+
+def test_pi_values_from_published_table():
+    vals = []
+    with open(os.path.join(HERE, "golden", "pi_values.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].split()
+            if line:
+                vals.append((int(line[0]), int(line[1])))
+    for x, pi in vals:
+        # base-prime generator: odd primes <= x plus the prime 2
+        assert len(O.odd_primes(x)) + 1 == pi, x
+    # the table itself: f = 0 and B = isqrt(v) gives zero bits exactly at the odd
+    # primes, so sum(counts) + 1 (for the prime 2) = pi(v)
+    for (l, n, x) in [(15, 64, 4194304), (16, 8, 1048576), (10, 32, 65536)]:
+        _, c = O.sieve(l, 0, n, math.isqrt(x))
+        pi = dict(vals)[x]
+        assert int(c.sum()) + 1 == pi
+
+
+def test_miller_rabin_every_bit_mid_interval():
+    # 2^16 numbers just above 10^12 and just below 2^62: every bit checked
+    for (l, f, n) in [(12, 10**12 // 2**13, 8), (12, 2**61 // 2**13 - 8, 8)]:
+        u, v = O.interval(l, f, n)
+        S, c = O.sieve(l, f, n, math.isqrt(v))
+        bits = bits_of(S)
+        for j in range(n << l):
+            assert bits[j] == (0 if is_prime_mr(u + 2 * j) else 1), (l, f, j)
+
+
+def test_miller_rabin_sampled_large_interval():
+    # a 2^25-number interval near 10^15 with the full base (B = isqrt(v))
+    l, n = 20, 16
+    f = 10**15 // 2**21
+    u, v = O.interval(l, f, n)
+    S, c = O.sieve(l, f, n, math.isqrt(v))
+    bits = bits_of(S)
+    rng = np.random.default_rng(11)
+    for j in rng.integers(0, n << l, 3000):
+        j = int(j)
+        assert bits[j] == (0 if is_prime_mr(u + 2 * j) else 1)
+    # every zero bit in the first 2^12 bits is a prime (density check on a block)
+    zeros = np.flatnonzero(bits[:4096] == 0)
+    assert all(is_prime_mr(u + 2 * int(j)) for j in zeros)
+    # prime number theorem sanity: density ~ 2/ln(N) over odd numbers
+    expect = (n << l) * 2 / math.log(u)
+    assert abs(int(c.sum()) - expect) < 0.01 * expect
+
+
+def test_partial_sieve_marks_only_small_factors():
+    # B < isqrt(v): a one bit must have an odd factor <= B; a zero bit must not
+    l, f, n, B = 12, 10**9 // 2**13, 4, 1000
+    u, v = O.interval(l, f, n)
+    S, _ = O.sieve(l, f, n, B)
+    bits = bits_of(S)
+    primes = [p for p in O.odd_primes(B)]
+    rng = np.random.default_rng(3)
+    for j in rng.integers(0, n << l, 2000):
+        N = u + 2 * int(j)
+        has = any(N % p == 0 and p < N for p in primes)
+        assert bits[int(j)] == (1 if has else 0)
+
+
+def test_lemma1_offset_brute_force():
+    rng = random.Random(5)
+    primes = [int(p) for p in O.odd_primes(5000)]
+    for _ in range(3000):
+        p = rng.choice(primes)
+        l = rng.randint(0, 40)
+        f = rng.randint(0, (1 << 63) >> l) if rng.random() < 0.7 else rng.randint(0, 100)
+        q = O.lemma1_offset(p, f, l)
+        assert 0 <= q < p
+        assert (2 * ((f << l) + q) + 1) % p == 0
+        # uniqueness: no smaller offset divides
+        if p < 200:
+            assert all((2 * ((f << l) + r) + 1) % p != 0 for r in range(q))
+
+
+def test_lemma2_skip_is_k_or_k_plus_1():
+    rng = random.Random(9)
+    primes = [int(p) for p in O.odd_primes(1 << 22)]
+    for _ in range(5000):
+        l = rng.randint(5, 20)
+        p = rng.choice(primes)
+        k = p >> l
+        q = rng.randrange(1 << l)
+        assert O.lemma2_skip(p, q, l) in (k, k + 1)
+
+
+def test_invalid_arguments_raise():
+    with pytest.raises(O.OracleError):
+        O.sieve(4, 0, 1, 3)          # l < 5
+    with pytest.raises(O.OracleError):
+        O.sieve(10, 0, 0, 3)         # n == 0
+    with pytest.raises(O.OracleError):
+        O.sieve(10, 0, 1, 2)         # B < 3
+    with pytest.raises(O.OracleError):
+        O.sieve(10, 0, 1, 1 << 32)   # B >= 2^32
+    with pytest.raises(O.OracleError):
+        O.sieve(20, (1 << 43), 1, 3)  # v >= 2^64
