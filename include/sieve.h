@@ -1,0 +1,181 @@
+/*
+ * sieve.h -- C ABI of the MI355X (gfx950) segmented odd-only sieve of Eratosthenes.
+ *
+ * The library computes the sieve table of Definition 1 (Section 1.3) of Jarai &
+ * Vatai, "Cache optimized linear sieve" (2011), for the interval of Section 1.2.1:
+ *
+ *     u = f * 2^(l+1) + 1,   v = (f + n) * 2^(l+1),
+ *
+ * a table S of n * 2^l bits in which bit j stands for the odd number u + 2j;
+ * bit j is 1 ("sieved out") iff u + 2j == 1 or u + 2j has an odd prime divisor
+ * p <= B with p < u + 2j, and 0 otherwise.  With B >= isqrt(v) the zero bits are
+ * exactly the odd primes in [u, v] (Section 1.4: the base is the primes up to
+ * sqrt(v)).  B < isqrt(v) is allowed and gives the partial sieve just defined.
+ * Bit j is bit (j % 32) of 32-bit word j / 32 (least significant bit first).
+ *
+ * counts[t] is the number of zero bits in segment t, i.e. in bits
+ * t*2^l .. (t+1)*2^l - 1 (Definition 1's segments S^(t)).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SIEVE_OK (0) on success, a negative sieve_status otherwise.
+ *    Nothing is enqueued when an argument check fails.  Faults that happen on the
+ *    device later surface as SIEVE_E_HIP from a later call or from
+ *    sieve_check_device_errors().
+ *  - Pointers named *_dev are device pointers (HIP device memory, e.g. the data
+ *    pointer of a torch.cuda tensor); the caller owns them and keeps them alive
+ *    until the stream work has finished.  Host pointers are only read during the
+ *    call.
+ *  - stream is a hipStream_t passed as void*; NULL means the null stream.  Work
+ *    is enqueued on it and the call returns without synchronising, except where
+ *    an entry point says otherwise.
+ *  - Validity: 5 <= l <= 20 (whole 32-bit words per segment), n >= 1,
+ *    v = (f+n)*2^(l+1) < 2^64, 3 <= B < 2^32 (the paper's 32-bit sieving primes,
+ *    Section 5).
+ *  - The library never calls back into Python and never throws.
+ */
+#ifndef SIEVE_MI355X_H
+#define SIEVE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIEVE_OK = 0,
+    SIEVE_E_ARG = -1,     /* l, n, a pointer or a tuning field is out of range        */
+    SIEVE_E_RANGE = -2,   /* v = (f+n)*2^(l+1) does not fit in 64 bits                */
+    SIEVE_E_BOUND = -3,   /* B < 3, B >= 2^32, or B above the prime table's bound     */
+    SIEVE_E_NOMEM = -4,   /* device allocation failed                                */
+    SIEVE_E_HIP = -5,     /* a HIP runtime call failed (see sieve_last_hip_error)     */
+    SIEVE_E_BUDGET = -6,  /* batch scratch would exceed the caller's byte budget      */
+    SIEVE_E_DEVICE = -7   /* a kernel reported a violated invariant (bucket overflow) */
+} sieve_status;
+
+/* Tuning knobs.  A zero field means "library default".  None of them can change
+ * the table or the counts (the result is unique given l, f, n, B); they only
+ * move work between kernels.
+ *   tile_log2   log2 of the LDS-resident tile in bits (the paper's cache segment,
+ *               Section 1.2); 13..20.  Default: l clamped to [15, 20].
+ *   medium_log2 primes below 2^medium_log2 are sieved per tile in LDS (Section
+ *               2.1 "medium primes"); primes at or above it take the bucket path
+ *               (Sections 2.2-2.5).  tile_log2-4 .. tile_log2+1.  Default tile_log2.
+ *   wave_log2   primes below 2^wave_log2 are sieved by a whole wavefront each,
+ *               larger medium primes by one lane each (the GPU form of the
+ *               per-hit-count grouping of Section 3.2.2).  Default tile_log2-6.
+ *   bins_log2   log2 of the number of large-prime buckets per chunk, 8..15.
+ *   groups      workgroups of the bucket-fill kernels, 64..2048. Default 512.
+ */
+typedef struct {
+    uint32_t tile_log2;
+    uint32_t medium_log2;
+    uint32_t wave_log2;
+    uint32_t bins_log2;
+    uint32_t groups;
+    uint32_t reserved[3];
+} sieve_tune;
+
+/* One interval of a batch: the interval of Section 1.2.1 with parameters
+ * (l, f, n) where l is the batch's l; S_dev holds n*2^l/32 words and counts_dev
+ * n words; B is this request's sieving bound (3 <= B <= the prime table's bound). */
+typedef struct {
+    uint64_t f;
+    uint64_t n;
+    uint64_t B;
+    uint32_t *S_dev;
+    uint32_t *counts_dev;
+} sieve_req;
+
+typedef struct sieve_ctx sieve_ctx;        /* library-owned device workspace        */
+typedef struct sieve_primes sieve_primes;  /* library-owned device sieving-prime table */
+
+/* --- one-shot entry point (Section 1.2.1 parameters l, f, n plus the bound B) ---
+ * Sieves the n segments of 2^l bits starting at segment f with the odd primes
+ * 3 <= p <= B, writing S_dev (n*2^l/32 uint32 words) and counts_dev (n uint32).
+ * Generates the sieving primes on the device (Section 1.4 initialization),
+ * computes the first offsets (Lemma 1), sieves each LDS tile with the pre-sieved
+ * pattern of 3..13, the medium primes (Section 2.1) and the bucketed large-prime
+ * hits (Sections 2.2-2.5), and writes each tile out with its popcount.
+ * Uses the calling thread's default context (one per device). */
+int sieve_init(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+               uint32_t *S_dev, uint32_t *counts_dev, void *stream);
+
+/* Same as sieve_init on an explicit context with explicit tuning (tune may be
+ * NULL).  Calls on one context are ordered by the context; contexts are
+ * independent, so two contexts may run on two streams at once. */
+int sieve_ctx_create(sieve_ctx **out);
+int sieve_ctx_destroy(sieve_ctx *ctx);   /* synchronises the context's last stream */
+int sieve_ctx_sieve(sieve_ctx *ctx, uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                    uint32_t *S_dev, uint32_t *counts_dev, const sieve_tune *tune,
+                    void *stream);
+
+/* --- shared sieving-prime table (Section 1.4, Definition 2: the base) ---
+ * Builds the odd primes 3 <= p <= B on the device and SYNCHRONISES the stream
+ * once, so that the prime count is known on the host. */
+int sieve_primes_create(uint64_t B, void *stream, sieve_primes **out);
+int sieve_primes_destroy(sieve_primes *pr);
+/* Number of primes in the table and its bound B. */
+int sieve_primes_info(const sieve_primes *pr, uint64_t *count, uint64_t *bound);
+/* Copies the first min(count, cap) primes (ascending uint32) to dst_dev. */
+int sieve_primes_copy(const sieve_primes *pr, uint32_t *dst_dev, uint64_t cap, void *stream);
+
+/* --- sieve with a shared table (no prime generation inside the call) --- */
+int sieve_ctx_sieve_with(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t f,
+                         uint64_t n, uint64_t B, uint32_t *S_dev, uint32_t *counts_dev,
+                         const sieve_tune *tune, void *stream);
+
+/* --- batched persistent launch ---
+ * Sieves every request of reqs[0..nreq) (all with segment size 2^l) against the
+ * one shared table pr: one offset kernel, one bucket fill and one persistent tile
+ * kernel for the whole batch, whose workgroups take (request, tile) work items
+ * from a device queue, longest first.  Each request's table and counts are the
+ * same as sieve_init would give for it alone. */
+int sieve_batch(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
+                size_t nreq, const sieve_tune *tune, void *stream);
+/* Device scratch bytes sieve_batch needs for these requests (bucket storage and
+ * per-request state; not counting the caller's S and counts), for admission
+ * control.  Pure host computation. */
+int sieve_batch_scratch_bytes(const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
+                              size_t nreq, const sieve_tune *tune, uint64_t *bytes);
+
+/* --- helpers --- */
+/* isqrt(v) for the interval (l, f, n): the bound that makes S an exact prime table. */
+int sieve_required_bound(uint32_t l, uint64_t f, uint64_t n, uint64_t *B);
+const char *sieve_strerror(int status);
+/* The last hipError_t seen by the library on this thread (0 if none). */
+int sieve_last_hip_error(void);
+/* Synchronises the context's stream and reports SIEVE_E_DEVICE if a kernel
+ * flagged a violated invariant since the last check (the flag is then cleared). */
+int sieve_check_device_errors(sieve_ctx *ctx);
+
+/* --- measurement ---
+ * When enabled, the context records a HIP event pair around every kernel it
+ * launches, on the stream it launches on, and accumulates the elapsed time per
+ * kernel name.  sieve_kernel_times synchronises and copies up to cap entries:
+ * names[i] (NUL-terminated, 47 chars max) and total milliseconds / launch counts. */
+int sieve_ctx_set_timing(sieve_ctx *ctx, int enable);
+int sieve_ctx_kernel_times(sieve_ctx *ctx, char (*names)[48], double *total_ms,
+                           uint64_t *launches, uint32_t cap, uint32_t *count);
+/* The default context used by sieve_init (created on first use). */
+sieve_ctx *sieve_default_ctx(void);
+/* Plain device copy of nbytes (multiple of 16) used to calibrate traffic counters. */
+int sieve_copy_calibration(const void *src_dev, void *dst_dev, uint64_t nbytes, void *stream);
+
+/* --- inspection (tests) ---
+ * Runs the offset and bucket-fill kernels for the first chunk of (l, f, n, B) and
+ * copies the bucket layout to host memory: bin_start (nbins+1 entries) and the
+ * 16-bit in-bin offsets of every large-prime hit (entries, up to cap).  Returns
+ * the number of bins in *nbins, the bin width log2 in *bin_log2, the number of
+ * bits covered in *chunk_bits and the number of large primes in *nlarge.
+ * Synchronises. */
+int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune *tune,
+                        uint32_t *bin_start_host, uint32_t bin_cap, uint16_t *entries_host,
+                        uint64_t entry_cap, uint32_t *nbins, uint32_t *bin_log2,
+                        uint64_t *chunk_bits, uint64_t *nlarge, uint64_t *nentries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIEVE_MI355X_H */

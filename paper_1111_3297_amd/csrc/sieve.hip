@@ -1,0 +1,738 @@
+// sieve.hip -- host runtime and C ABI of the MI355X segmented odd-only sieve.
+// The entry points are declared and documented in include/sieve.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sieve.h"
+#include "kernels.inc"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) {                            \
+      g_last_hip = (int)e_;                            \
+      return SIEVE_E_HIP;                              \
+    }                                                  \
+  } while (0)
+
+#define STCHK(expr)                 \
+  do {                              \
+    int s_ = (expr);                \
+    if (s_ != SIEVE_OK) return s_;  \
+  } while (0)
+
+constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
+constexpr uint32_t kGenTile = 20;             // tile of the prime generator
+constexpr uint32_t kMagicLimit = 1u << 22;    // Barrett constants for primes below this
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t n) {
+    if (n <= bytes) return SIEVE_OK;
+    if (p) {
+      // previous users on any stream must be done before the memory is released
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) { g_last_hip = (int)e; return SIEVE_E_HIP; }
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) { g_last_hip = (int)e; p = nullptr; return SIEVE_E_NOMEM; }
+    bytes = want;
+    return SIEVE_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Rosser-Schoenfeld style bounds (all primes, so they also bound the odd ones).
+uint64_t pi_upper(uint64_t x) {
+  if (x < 100) return 26;
+  double v = 1.25506 * (double)x / std::log((double)x);
+  return (uint64_t)v + 64;
+}
+// Upper bound on sum of 1/p for lo <= p <= hi (lo >= 286): loglog(hi) - loglog(lo) + 1/ln^2(lo).
+double recip_sum_upper(double lo, double hi) {
+  if (hi < lo) return 0.0;
+  lo = std::max(lo, 286.0);
+  double l1 = std::log(lo);
+  return std::log(std::log(std::max(hi, lo))) - std::log(l1) + 1.0 / (l1 * l1);
+}
+
+uint64_t isqrt_u64(uint64_t x) {
+  uint64_t r = (uint64_t)std::sqrt((double)x);
+  while (r > 0 && (unsigned __int128)r * r > x) --r;
+  while ((unsigned __int128)(r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
+struct Resolved {
+  uint32_t L, Mlog, Wlog, binslog, groups;
+};
+
+int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
+  sieve_tune z;
+  memset(&z, 0, sizeof z);
+  if (!t) t = &z;
+  r->L = t->tile_log2 ? t->tile_log2 : std::min<uint32_t>(20, std::max<uint32_t>(15, l));
+  if (r->L < 13 || r->L > 20 || r->L > l + 10) return SIEVE_E_ARG;  // per-tile count slots fit LDS
+  r->Mlog = t->medium_log2 ? t->medium_log2 : r->L;
+  if (r->Mlog + 4 < r->L || r->Mlog > r->L + 1) return SIEVE_E_ARG;
+  r->Wlog = t->wave_log2 ? t->wave_log2 : r->L - 6;
+  if (r->Wlog < 5 || r->Wlog > r->Mlog) return SIEVE_E_ARG;
+  r->binslog = t->bins_log2 ? t->bins_log2 : 14;
+  if (r->binslog < 8 || r->binslog > 15) return SIEVE_E_ARG;
+  r->groups = t->groups ? t->groups : 512;
+  if (r->groups < 64 || r->groups > 2048) return SIEVE_E_ARG;
+  return SIEVE_OK;
+}
+
+int check_interval(uint32_t l, uint64_t f, uint64_t n, uint64_t B, uint64_t* F, uint64_t* NB) {
+  if (l < 5 || l > 20 || n == 0) return SIEVE_E_ARG;
+  if (B < 3 || B >= (1ull << 32)) return SIEVE_E_BOUND;
+  unsigned __int128 FF = (unsigned __int128)f << l, NN = (unsigned __int128)n << l;
+  unsigned __int128 v = 2 * (FF + NN);
+  if (v >> 64) return SIEVE_E_RANGE;
+  *F = (uint64_t)FF;
+  *NB = (uint64_t)NN;
+  return SIEVE_OK;
+}
+
+}  // namespace
+
+struct sieve_primes {
+  int device = 0;
+  uint64_t B = 0;
+  uint64_t count = 0;
+  DevBuf P, M, cnt;
+};
+
+struct KernelTime {
+  double ms = 0;
+  uint64_t n = 0;
+};
+
+struct sieve_ctx {
+  std::mutex mu;
+  int device = 0;
+  hipStream_t last_stream = nullptr;
+  bool has_last = false;
+  hipEvent_t done = nullptr;
+  // scratch
+  DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk;
+  DevBuf pat[32];
+  uint32_t pat_words[32] = {0};
+  sieve_primes own;  // table built by sieve_init / sieve_ctx_sieve
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending { std::string name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::map<std::string, KernelTime> times;
+  ~sieve_ctx();
+};
+
+sieve_ctx::~sieve_ctx() {
+  if (has_last) (void)hipStreamSynchronize(last_stream);
+  DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk,
+                    &own.P, &own.M, &own.cnt};
+  for (DevBuf* b : bufs) b->release();
+  for (auto& b : pat) b.release();
+  for (auto& e : ev_pool) (void)hipEventDestroy(e);
+  for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  if (done) (void)hipEventDestroy(done);
+}
+
+namespace {
+
+hipEvent_t take_event(sieve_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch wrapper: records an event pair around the kernel when timing is on.
+template <typename F>
+int launch(sieve_ctx* c, const char* name, hipStream_t s, F&& f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->timing) {
+    a = take_event(c);
+    b = take_event(c);
+    if (a && b) HIPCHK(hipEventRecord(a, s));
+  }
+  f();
+  HIPCHK(hipGetLastError());
+  if (c->timing && a && b) {
+    HIPCHK(hipEventRecord(b, s));
+    c->pending.push_back({name, a, b});
+  }
+  return SIEVE_OK;
+}
+
+int collect_times(sieve_ctx* c) {
+  for (auto& p : c->pending) {
+    HIPCHK(hipEventSynchronize(p.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& kt = c->times[p.name];
+    kt.ms += ms;
+    kt.n += 1;
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+  return SIEVE_OK;
+}
+
+int set_lds_limits() {
+  static std::once_flag once;
+  static int rc = SIEVE_OK;
+  std::call_once(once, [] {
+    const int lim = 160 * 1024;
+    if (hipFuncSetAttribute((const void*)sv::k_tile, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+        hipFuncSetAttribute((const void*)sv::k_bucket_count, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+        hipFuncSetAttribute((const void*)sv::k_bucket_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+      rc = SIEVE_E_HIP;
+  });
+  return rc;
+}
+
+// Pattern of the primes 3..13 that are <= B (Section 3.1's small primes, applied
+// as one periodic mask instead of per-prime masks).
+int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, uint32_t* per,
+                uint32_t* words, uint32_t* mask) {
+  static const uint32_t small[5] = {3, 5, 7, 11, 13};
+  uint32_t m = 0, P = 1;
+  for (int i = 0; i < 5; ++i)
+    if (small[i] <= B) { m |= 1u << i; P *= small[i]; }
+  const uint32_t nw = (P + 64 + 31) / 32;
+  if (!c->pat_words[m]) {
+    STCHK(c->pat[m].ensure((size_t)nw * 4));
+    STCHK(launch(c, "k_pattern", s, [&] {
+      sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->pat[m].as<uint32_t>(), P, m, nw);
+    }));
+    c->pat_words[m] = nw;
+  }
+  *pat = c->pat[m].as<uint32_t>();
+  *per = P;
+  *words = nw;
+  *mask = m;
+  return SIEVE_OK;
+}
+
+size_t tile_lds_bytes(uint32_t L, uint32_t l, uint32_t patw) {
+  uint32_t nseg = (L >= l) ? (1u << (L - l)) : 1u;
+  return ((size_t)(1u << (L - 5)) + patw + nseg + 1) * 4;
+}
+
+// Builds the odd primes 3 <= p <= B into pr (device count in pr->cnt).
+int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
+  const uint64_t cap = pi_upper(B) + 16;
+  STCHK(pr->P.ensure(cap * 4));
+  STCHK(pr->M.ensure(std::min<uint64_t>(cap, pi_upper(kMagicLimit)) * 4));
+  STCHK(pr->cnt.ensure(16));
+  uint32_t* P = pr->P.as<uint32_t>();
+  uint32_t* cnt = pr->cnt.as<uint32_t>();
+  if (B < 65536) {
+    STCHK(launch(c, "k_base_primes", s, [&] { sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)B, P, cnt); }));
+  } else {
+    // base primes up to isqrt(B) < 2^16, then one sieve of the odd numbers 1..B
+    const uint64_t rb = isqrt_u64(B);
+    STCHK(c->gen_blk.ensure(pi_upper(65536) * 4 + 64));
+    uint32_t* base = c->gen_blk.as<uint32_t>();
+    uint32_t* base_cnt = base + pi_upper(65536);
+    STCHK(launch(c, "k_base_primes", s, [&] { sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)rb, base, base_cnt); }));
+    const uint32_t nbase_ub = (uint32_t)pi_upper(65536);
+    STCHK(pr->M.ensure(std::max<uint64_t>(pr->M.bytes, (uint64_t)nbase_ub * 4)));
+    STCHK(launch(c, "k_magic", s, [&] {
+      sv::k_magic<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, base_cnt, pr->M.as<uint32_t>(), nbase_ub);
+    }));
+    STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
+    sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
+    STCHK(launch(c, "k_plan", s, [&] {
+      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, 1ull << (kGenTile - 6), 1ull << 17, gplan);
+    }));
+    // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
+    // 2^15-bit count segments (the extra bits are masked off by the compaction)
+    const uint64_t kmax = (B - 1) / 2;
+    const uint32_t gl = 15;
+    const uint64_t gbits = ((kmax + 1 + (1ull << gl) - 1) >> gl) << gl;
+    const uint32_t L = kGenTile;
+    const uint32_t ntiles = (uint32_t)((gbits + (1ull << L) - 1) >> L);
+    const uint32_t nwords = (uint32_t)(gbits / 32);
+    const uint32_t nblk = (nwords + 1023) / 1024;
+    const uint32_t ncnt = (uint32_t)(gbits >> gl);
+    STCHK(c->gen_S.ensure(((size_t)nwords + nblk + ncnt + 64) * 4));
+    uint32_t* gS = c->gen_S.as<uint32_t>();
+    uint32_t* gblk = gS + nwords;
+    uint32_t* gcounts = gblk + nblk + 32;
+    STCHK(c->Q0.ensure(pi_upper(65536) * 4));
+    STCHK(launch(c, "k_offsets", s, [&] {
+      sv::k_offsets<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, gplan, 0, gbits, c->Q0.as<uint32_t>(), nullptr);
+    }));
+    const uint32_t* pat; uint32_t per, patw, pmask;
+    STCHK(get_pattern(c, rb, s, &pat, &per, &patw, &pmask));
+    sv::TileArgs ta;
+    memset(&ta, 0, sizeof ta);
+    ta.G0 = 0; ta.lbits = (uint32_t)gbits; ta.t0 = 0; ta.L = L; ta.l = gl;
+    ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = 0; ta.per_tile = (uint32_t)((1ull << L) % per);
+    ta.fixmask = pmask; ta.P = base; ta.M = pr->M.as<uint32_t>(); ta.Q0 = c->Q0.as<uint32_t>();
+    ta.plan = gplan; ta.psq = 1; ta.has_large = 0; ta.b = 16;
+    ta.S = gS; ta.counts = gcounts; ta.count_atomic = 0;
+    STCHK(launch(c, "k_tile[gen]", s, [&] {
+      sv::k_tile<<<ntiles, 1024, tile_lds_bytes(L, gl, patw), s>>>(ta);
+    }));
+    STCHK(launch(c, "k_compact_count", s, [&] {
+      sv::k_compact_count<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk);
+    }));
+    STCHK(launch(c, "k_scan_small", s, [&] { sv::k_scan_small<<<1, 1024, 0, s>>>(gblk, nblk, cnt); }));
+    STCHK(launch(c, "k_compact_write", s, [&] {
+      sv::k_compact_write<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk, P);
+    }));
+  }
+  const uint64_t mlim = std::min<uint64_t>(cap, pi_upper(kMagicLimit));
+  STCHK(launch(c, "k_magic", s, [&] {
+    sv::k_magic<<<(uint32_t)((mlim + 255) / 256), 256, 0, s>>>(P, cnt, pr->M.as<uint32_t>(), (uint32_t)mlim);
+  }));
+  pr->B = B;
+  return SIEVE_OK;
+}
+
+// Device error word: allocated and cleared once per context.
+int ensure_err(sieve_ctx* c, hipStream_t s) {
+  if (c->err.p) return SIEVE_OK;
+  STCHK(c->err.ensure(64));
+  sv::k_fill_u32<<<1, 64, 0, s>>>(c->err.as<uint32_t>(), 16, 0);
+  HIPCHK(hipGetLastError());
+  return SIEVE_OK;
+}
+
+// The sieve proper for one request (l, F, NB) with the table pr and bound B.
+int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint64_t NB, uint64_t B,
+              uint32_t* S, uint32_t* counts, const Resolved& R, hipStream_t s) {
+  const uint32_t L = R.L;
+  const uint64_t wave_lim = 1ull << R.Wlog, med_lim = 1ull << R.Mlog;
+  const uint64_t tab_ub = std::min<uint64_t>(pi_upper(B), pi_upper(pr->B));
+  STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
+  sv::Plan* plan = c->plan.as<sv::Plan>();
+  STCHK(launch(c, "k_plan", s, [&] {
+    sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, wave_lim, med_lim, plan);
+  }));
+  const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
+  STCHK(c->Q0.ensure(med_ub * 4 + 64));
+  const bool large = B >= med_lim;
+  const uint64_t nL_ub = large ? tab_ub : 0;
+  if (large) STCHK(c->OFF.ensure(nL_ub * 4 + 64));
+  const uint32_t* pat; uint32_t per, patw, pmask;
+  STCHK(get_pattern(c, B, s, &pat, &per, &patw, &pmask));
+  const uint32_t b = std::min<uint32_t>(L, 16);
+  const uint32_t G = R.groups;
+  const uint64_t chunk_max = (1ull << R.binslog) << b;        // bits per bucket fill
+  const uint32_t splits = (G + 15) / 16;
+  if (large) {
+    STCHK(c->HG.ensure((size_t)G << R.binslog << 2));
+    STCHK(c->PS.ensure((size_t)splits << R.binslog << 2));
+    STCHK(c->bstart.ensure(((1ull << R.binslog) + 1) * 4));
+    const uint64_t cb = std::min<uint64_t>(chunk_max, NB);
+    const double rs = recip_sum_upper((double)med_lim, (double)B);
+    const uint64_t cap = (uint64_t)(1.02 * rs * (double)cb) + nL_ub + 4096;
+    if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
+    STCHK(c->bucket.ensure(cap * 2));
+  }
+  STCHK(ensure_err(c, s));
+  const bool count_atomic = L < l;
+  if (count_atomic) {
+    const uint64_t n = NB >> l;
+    STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(counts, n, 0); }));
+  }
+  const uint32_t patG_step = (uint32_t)((1ull << L) % per);
+  for (uint64_t ls = 0; ls < NB; ls += kLaunchBits) {
+    const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB - ls);
+    const uint64_t G0 = F + ls;
+    const uint64_t off_ub = tab_ub;  // grid over primes >= 17
+    STCHK(launch(c, "k_offsets", s, [&] {
+      sv::k_offsets<<<(uint32_t)((off_ub + 255) / 256), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, lbits,
+                                                                     c->Q0.as<uint32_t>(), large ? c->OFF.as<uint32_t>() : nullptr);
+    }));
+    const uint64_t psq = isqrt_u64(2 * G0 + 1);
+    for (uint64_t cs = 0; cs < lbits; cs += chunk_max) {
+      const uint64_t cbits = std::min<uint64_t>(chunk_max, lbits - cs);
+      const uint32_t ntiles = (uint32_t)((cbits + (1ull << L) - 1) >> L);
+      const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
+      const double rs = large ? recip_sum_upper((double)med_lim, (double)B) : 0;
+      const uint64_t cap = (uint64_t)(1.02 * rs * (double)std::min<uint64_t>(chunk_max, NB)) + nL_ub + 4096;
+      if (large) {
+        sv::BucketArgs ba;
+        ba.P = pr->P.as<uint32_t>(); ba.plan = plan; ba.OFF = c->OFF.as<uint32_t>();
+        ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins;
+        const size_t hl = (size_t)nbins * 4;
+        STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count<<<G, 1024, hl, s>>>(ba, c->HG.as<uint32_t>()); }));
+        STCHK(launch(c, "k_bin_colsum", s, [&] {
+          sv::k_bin_colsum<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
+        }));
+        STCHK(launch(c, "k_bin_scan", s, [&] {
+          sv::k_bin_scan<<<1, 1024, 0, s>>>(c->PS.as<uint32_t>(), splits, nbins, c->bstart.as<uint32_t>());
+        }));
+        STCHK(launch(c, "k_bin_colprefix", s, [&] {
+          sv::k_bin_colprefix<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
+        }));
+        STCHK(launch(c, "k_bucket_scatter", s, [&] {
+          sv::k_bucket_scatter<<<G, 1024, hl, s>>>(ba, c->HG.as<uint32_t>(), c->bucket.as<uint16_t>(), (uint32_t)cap,
+                                                   c->err.as<uint32_t>());
+        }));
+      }
+      sv::TileArgs ta;
+      memset(&ta, 0, sizeof ta);
+      ta.G0 = G0; ta.lbits = (uint32_t)lbits; ta.t0 = (uint32_t)(cs >> L); ta.L = L; ta.l = l;
+      ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
+      ta.fixmask = pmask; ta.P = pr->P.as<uint32_t>(); ta.M = pr->M.as<uint32_t>(); ta.Q0 = c->Q0.as<uint32_t>();
+      ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
+      ta.bucket = large ? c->bucket.as<uint16_t>() : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
+      ta.b = b; ta.nbins = nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
+      ta.S = S + (ls >> 5); ta.counts = counts + (ls >> l); ta.count_atomic = count_atomic ? 1 : 0;
+      STCHK(launch(c, "k_tile", s, [&] { sv::k_tile<<<ntiles, 1024, tile_lds_bytes(L, l, patw), s>>>(ta); }));
+    }
+  }
+  return SIEVE_OK;
+}
+
+int begin(sieve_ctx* c, hipStream_t s) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  c->device = dev;
+  STCHK(set_lds_limits());
+  if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
+  return SIEVE_OK;
+}
+
+int end(sieve_ctx* c, hipStream_t s) {
+  if (!c->done) HIPCHK(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(c->done, s));
+  c->last_stream = s;
+  c->has_last = true;
+  return SIEVE_OK;
+}
+
+std::mutex g_default_mu;
+std::map<int, sieve_ctx*> g_default;
+
+}  // namespace
+
+extern "C" {
+
+int sieve_ctx_create(sieve_ctx** out) {
+  if (!out) return SIEVE_E_ARG;
+  *out = new (std::nothrow) sieve_ctx();
+  return *out ? SIEVE_OK : SIEVE_E_NOMEM;
+}
+
+int sieve_ctx_destroy(sieve_ctx* ctx) {
+  if (!ctx) return SIEVE_E_ARG;
+  delete ctx;
+  return SIEVE_OK;
+}
+
+sieve_ctx* sieve_default_ctx(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> g(g_default_mu);
+  auto it = g_default.find(dev);
+  if (it != g_default.end()) return it->second;
+  sieve_ctx* c = new (std::nothrow) sieve_ctx();
+  if (c) g_default[dev] = c;
+  return c;
+}
+
+int sieve_ctx_sieve(sieve_ctx* ctx, uint32_t l, uint64_t f, uint64_t n, uint64_t B, uint32_t* S_dev,
+                    uint32_t* counts_dev, const sieve_tune* tune, void* stream) {
+  if (!ctx || !S_dev || !counts_dev) return SIEVE_E_ARG;
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, B, &F, &NB));
+  Resolved R;
+  STCHK(resolve_tune(l, tune, &R));
+  std::lock_guard<std::mutex> g(ctx->mu);
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(ctx, s));
+  STCHK(build_primes(ctx, B, &ctx->own, s));
+  STCHK(run_sieve(ctx, &ctx->own, l, F, NB, B, S_dev, counts_dev, R, s));
+  return end(ctx, s);
+}
+
+int sieve_init(uint32_t l, uint64_t f, uint64_t n, uint64_t B, uint32_t* S_dev, uint32_t* counts_dev,
+               void* stream) {
+  // argument checks come before any HIP call
+  if (!S_dev || !counts_dev) return SIEVE_E_ARG;
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, B, &F, &NB));
+  sieve_ctx* c = sieve_default_ctx();
+  if (!c) return SIEVE_E_HIP;
+  return sieve_ctx_sieve(c, l, f, n, B, S_dev, counts_dev, nullptr, stream);
+}
+
+int sieve_primes_create(uint64_t B, void* stream, sieve_primes** out) {
+  if (!out) return SIEVE_E_ARG;
+  *out = nullptr;
+  if (B < 3 || B >= (1ull << 32)) return SIEVE_E_BOUND;
+  sieve_ctx* c = sieve_default_ctx();
+  if (!c) return SIEVE_E_HIP;
+  sieve_primes* pr = new (std::nothrow) sieve_primes();
+  if (!pr) return SIEVE_E_NOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    rc = begin(c, s);
+    if (rc == SIEVE_OK) rc = build_primes(c, B, pr, s);
+    if (rc == SIEVE_OK) rc = end(c, s);
+  }
+  uint32_t cnt = 0;
+  if (rc == SIEVE_OK) {
+    hipError_t e = hipMemcpyAsync(&cnt, pr->cnt.p, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { g_last_hip = (int)e; rc = SIEVE_E_HIP; }
+  }
+  if (rc != SIEVE_OK) { pr->P.release(); pr->M.release(); pr->cnt.release(); delete pr; return rc; }
+  pr->count = cnt;
+  pr->device = c->device;
+  *out = pr;
+  return SIEVE_OK;
+}
+
+int sieve_primes_destroy(sieve_primes* pr) {
+  if (!pr) return SIEVE_E_ARG;
+  (void)hipDeviceSynchronize();
+  pr->P.release(); pr->M.release(); pr->cnt.release();
+  delete pr;
+  return SIEVE_OK;
+}
+
+int sieve_primes_info(const sieve_primes* pr, uint64_t* count, uint64_t* bound) {
+  if (!pr) return SIEVE_E_ARG;
+  if (count) *count = pr->count;
+  if (bound) *bound = pr->B;
+  return SIEVE_OK;
+}
+
+int sieve_primes_copy(const sieve_primes* pr, uint32_t* dst_dev, uint64_t cap, void* stream) {
+  if (!pr || !dst_dev) return SIEVE_E_ARG;
+  uint64_t n = std::min(cap, pr->count);
+  if (n) HIPCHK(hipMemcpyAsync(dst_dev, pr->P.p, n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SIEVE_OK;
+}
+
+int sieve_ctx_sieve_with(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                         uint32_t* S_dev, uint32_t* counts_dev, const sieve_tune* tune, void* stream) {
+  if (!ctx || !pr || !S_dev || !counts_dev) return SIEVE_E_ARG;
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, B, &F, &NB));
+  if (B > pr->B) return SIEVE_E_BOUND;
+  Resolved R;
+  STCHK(resolve_tune(l, tune, &R));
+  std::lock_guard<std::mutex> g(ctx->mu);
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(ctx, s));
+  STCHK(run_sieve(ctx, pr, l, F, NB, B, S_dev, counts_dev, R, s));
+  return end(ctx, s);
+}
+
+int sieve_required_bound(uint32_t l, uint64_t f, uint64_t n, uint64_t* B) {
+  if (!B) return SIEVE_E_ARG;
+  if (l < 5 || l > 20 || n == 0) return SIEVE_E_ARG;
+  unsigned __int128 v = (((unsigned __int128)f + n) << (l + 1));
+  if (v >> 64) return SIEVE_E_RANGE;
+  *B = isqrt_u64((uint64_t)v);
+  return SIEVE_OK;
+}
+
+const char* sieve_strerror(int st) {
+  switch (st) {
+    case SIEVE_OK: return "ok";
+    case SIEVE_E_ARG: return "invalid argument";
+    case SIEVE_E_RANGE: return "interval end v does not fit in 64 bits";
+    case SIEVE_E_BOUND: return "sieving bound B out of range";
+    case SIEVE_E_NOMEM: return "device allocation failed";
+    case SIEVE_E_HIP: return "HIP runtime error";
+    case SIEVE_E_BUDGET: return "batch exceeds the byte budget";
+    case SIEVE_E_DEVICE: return "device kernel reported a violated invariant";
+    default: return "unknown status";
+  }
+}
+
+int sieve_last_hip_error(void) { return g_last_hip; }
+
+int sieve_check_device_errors(sieve_ctx* ctx) {
+  if (!ctx) return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (!ctx->err.p) return SIEVE_OK;
+  uint32_t v = 0;
+  if (ctx->has_last) HIPCHK(hipStreamSynchronize(ctx->last_stream));
+  HIPCHK(hipMemcpy(&v, ctx->err.p, 4, hipMemcpyDeviceToHost));
+  if (v) {
+    uint32_t z = 0;
+    HIPCHK(hipMemcpy(ctx->err.p, &z, 4, hipMemcpyHostToDevice));
+    return SIEVE_E_DEVICE;
+  }
+  return SIEVE_OK;
+}
+
+int sieve_ctx_set_timing(sieve_ctx* ctx, int enable) {
+  if (!ctx) return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->timing = enable != 0;
+  if (!enable) { ctx->times.clear(); }
+  return SIEVE_OK;
+}
+
+int sieve_ctx_kernel_times(sieve_ctx* ctx, char (*names)[48], double* total_ms, uint64_t* launches, uint32_t cap,
+                           uint32_t* count) {
+  if (!ctx || !count) return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  STCHK(collect_times(ctx));
+  uint32_t i = 0;
+  for (auto& kv : ctx->times) {
+    if (i < cap) {
+      if (names) { strncpy(names[i], kv.first.c_str(), 47); names[i][47] = 0; }
+      if (total_ms) total_ms[i] = kv.second.ms;
+      if (launches) launches[i] = kv.second.n;
+    }
+    ++i;
+  }
+  *count = i;
+  ctx->times.clear();
+  return SIEVE_OK;
+}
+
+int sieve_copy_calibration(const void* src_dev, void* dst_dev, uint64_t nbytes, void* stream) {
+  if (!src_dev || !dst_dev || (nbytes % 16)) return SIEVE_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  sv::k_copy16<<<2048, 256, 0, s>>>((const uint4*)src_dev, (uint4*)dst_dev, nbytes / 16);
+  HIPCHK(hipGetLastError());
+  return SIEVE_OK;
+}
+
+int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune* tune,
+                        uint32_t* bin_start_host, uint32_t bin_cap, uint16_t* entries_host, uint64_t entry_cap,
+                        uint32_t* nbins_out, uint32_t* bin_log2, uint64_t* chunk_bits, uint64_t* nlarge,
+                        uint64_t* nentries) {
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, B, &F, &NB));
+  Resolved R;
+  STCHK(resolve_tune(l, tune, &R));
+  if (!bin_start_host || !nbins_out) return SIEVE_E_ARG;
+  sieve_ctx* c = sieve_default_ctx();
+  if (!c) return SIEVE_E_HIP;
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t s = nullptr;
+  STCHK(begin(c, s));
+  STCHK(build_primes(c, B, &c->own, s));
+  const uint64_t med_lim = 1ull << R.Mlog;
+  if (B < med_lim) return SIEVE_E_ARG;  // no large primes
+  const uint64_t tab_ub = pi_upper(B);
+  STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
+  sv::Plan* plan = c->plan.as<sv::Plan>();
+  sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 1ull << R.Wlog, med_lim, plan);
+  STCHK(c->Q0.ensure(tab_ub * 4 + 64));
+  STCHK(c->OFF.ensure(tab_ub * 4 + 64));
+  const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB);
+  sv::k_offsets<<<(uint32_t)((tab_ub + 255) / 256), 256, 0, s>>>(c->own.P.as<uint32_t>(), plan, F, lbits,
+                                                                 c->Q0.as<uint32_t>(), c->OFF.as<uint32_t>());
+  const uint32_t b = std::min<uint32_t>(R.L, 16);
+  const uint64_t cbits = std::min<uint64_t>((1ull << R.binslog) << b, lbits);
+  const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
+  const uint32_t G = R.groups, splits = (G + 15) / 16;
+  STCHK(c->HG.ensure((size_t)G * nbins * 4));
+  STCHK(c->PS.ensure((size_t)splits * nbins * 4));
+  STCHK(c->bstart.ensure((nbins + 1) * 4));
+  const double rs = recip_sum_upper((double)med_lim, (double)B);
+  const uint64_t cap = (uint64_t)(1.02 * rs * (double)cbits) + tab_ub + 4096;
+  STCHK(c->bucket.ensure(cap * 2));
+  STCHK(ensure_err(c, s));
+  sv::BucketArgs ba;
+  ba.P = c->own.P.as<uint32_t>(); ba.plan = plan; ba.OFF = c->OFF.as<uint32_t>();
+  ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins;
+  sv::k_bucket_count<<<G, 1024, nbins * 4, s>>>(ba, c->HG.as<uint32_t>());
+  sv::k_bin_colsum<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
+  sv::k_bin_scan<<<1, 1024, 0, s>>>(c->PS.as<uint32_t>(), splits, nbins, c->bstart.as<uint32_t>());
+  sv::k_bin_colprefix<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
+  sv::k_bucket_scatter<<<G, 1024, nbins * 4, s>>>(ba, c->HG.as<uint32_t>(), c->bucket.as<uint16_t>(), (uint32_t)cap,
+                                                   c->err.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<uint32_t> bs(nbins + 1);
+  HIPCHK(hipMemcpy(bs.data(), c->bstart.p, (nbins + 1) * 4, hipMemcpyDeviceToHost));
+  uint32_t np_cnt = 0;
+  sv::Plan hp;
+  HIPCHK(hipMemcpy(&hp, plan, sizeof hp, hipMemcpyDeviceToHost));
+  (void)np_cnt;
+  if (nbins_out) *nbins_out = nbins;
+  if (bin_log2) *bin_log2 = b;
+  if (chunk_bits) *chunk_bits = cbits;
+  if (nlarge) *nlarge = hp.np - hp.iM;
+  if (nentries) *nentries = bs[nbins];
+  if (bin_start_host) memcpy(bin_start_host, bs.data(), std::min<uint32_t>(bin_cap, nbins + 1) * 4);
+  if (entries_host) {
+    uint64_t ne = std::min<uint64_t>(entry_cap, bs[nbins]);
+    if (ne) HIPCHK(hipMemcpy(entries_host, c->bucket.p, ne * 2, hipMemcpyDeviceToHost));
+  }
+  uint32_t ev = 0;
+  HIPCHK(hipMemcpy(&ev, c->err.p, 4, hipMemcpyDeviceToHost));
+  if (ev) {
+    uint32_t z = 0;
+    HIPCHK(hipMemcpy(c->err.p, &z, 4, hipMemcpyHostToDevice));
+    return SIEVE_E_DEVICE;
+  }
+  return end(c, s);
+}
+
+int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_req* reqs, size_t nreq,
+                const sieve_tune* tune, void* stream) {
+  // Interim: requests run back to back on the shared table (replaced by the
+  // persistent batched launch).
+  if (!ctx || !pr || (!reqs && nreq)) return SIEVE_E_ARG;
+  for (size_t i = 0; i < nreq; ++i)
+    STCHK(sieve_ctx_sieve_with(ctx, pr, l, reqs[i].f, reqs[i].n, reqs[i].B, reqs[i].S_dev, reqs[i].counts_dev,
+                               tune, stream));
+  return SIEVE_OK;
+}
+
+int sieve_batch_scratch_bytes(const sieve_primes* pr, uint32_t l, const sieve_req* reqs, size_t nreq,
+                              const sieve_tune* tune, uint64_t* bytes) {
+  if (!pr || !bytes || (!reqs && nreq)) return SIEVE_E_ARG;
+  Resolved R;
+  STCHK(resolve_tune(l, tune, &R));
+  uint64_t tot = 0;
+  for (size_t i = 0; i < nreq; ++i) {
+    const uint64_t NB = reqs[i].n << l;
+    const double rs = recip_sum_upper((double)(1ull << R.Mlog), (double)reqs[i].B);
+    tot += (uint64_t)(1.02 * rs * (double)NB) * 2 + pi_upper(reqs[i].B) * 8;
+  }
+  *bytes = tot;
+  return SIEVE_OK;
+}
+
+}  // extern "C"

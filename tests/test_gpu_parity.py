@@ -1,0 +1,172 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for bit.
+
+Every table bit and every per-segment count must be identical (integer work, one
+correct answer).  Small cases compare whole tables with the oracle; the
+full-size workloads compare per-segment counts and the SHA-256 of the whole
+table with values the oracle wrote (tests/golden/make_golden.py).
+"""
+import json
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.gpu_util import say, gpu_sieve, sha256_words, first_diff
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def check_case(l, f, n, B, tune=None, **kw):
+    say("case l=%d f=%d n=%d B=%d tune=%s" % (l, f, n, B, tune))
+    S, c = gpu_sieve(l, f, n, B, tune=tune, **kw)
+    So, co = O.sieve(l, f, n, B)
+    assert first_diff(S, So) is None, ("table", l, f, n, B, tune, first_diff(S, So))
+    assert np.array_equal(c, co), ("counts", l, f, n, B, tune)
+    return S, c
+
+
+def test_small_config_pi_2_22():
+    # l=15, f=0, n=64 sieves 1..2^22 with primes <= 2048: pi(2^22) = 295947
+    S, c = check_case(15, 0, 64, 2048)
+    assert int(c.sum()) + 1 == 295947
+    assert int(c[0]) == 6541
+
+
+@pytest.mark.parametrize("case", [
+    (5, 0, 1, 3), (5, 0, 1, 13), (6, 0, 3, 17), (10, 0, 4, 1000), (11, 0, 16, 3),
+    (12, 5, 7, 61), (16, 0, 1, 65535), (20, 0, 2, 65536), (20, 0, 1, 65537),
+    (18, 1, 3, 2000), (13, 1000, 9, 200003),
+])
+def test_edge_cases(case):
+    check_case(*case)
+
+
+def test_near_2_64_partial_sieve():
+    # v = (f+n)*2^21 = 2^64 - 2^22: the largest interval end the interface allows
+    check_case(20, 2**43 - 2, 1, 10**6)
+    check_case(20, 2**43 - 3, 2, 3)
+
+
+def test_random_small_with_tunings():
+    rng = random.Random(20111111)
+    tunings = [None,
+               {"tile_log2": 13, "medium_log2": 9, "wave_log2": 6, "bins_log2": 8, "groups": 64},
+               {"tile_log2": 14, "medium_log2": 12, "wave_log2": 8, "bins_log2": 9},
+               {"tile_log2": 17, "medium_log2": 14, "wave_log2": 10},
+               {"tile_log2": 15, "medium_log2": 16, "wave_log2": 5, "bins_log2": 10, "groups": 128}]
+    for k in range(40):
+        l = rng.choice([5, 7, 11, 13, 15, 16, 17])
+        n = rng.randint(1, max(1, (1 << 21) >> l))
+        e = rng.choice([0, 3, 6, 9, 12, 15, 18])
+        f = (10**e) >> (l + 1) if e else 0
+        f += rng.randint(0, 50)
+        u, v = O.interval(l, f, n)
+        r = math.isqrt(v)
+        B = rng.choice([r, r, max(3, r // 7), min(r, 5 * 10**5) if r > 3 else 3])
+        B = max(3, min(B, 2**24))
+        tune = tunings[k % len(tunings)]
+        if tune is not None and tune["tile_log2"] > l + 10:   # per-tile count slots must fit LDS
+            tune = dict(tune, tile_log2=l + 10, medium_log2=min(tune["medium_log2"], l + 11),
+                        wave_log2=min(tune["wave_log2"], l + 10))
+            tune["medium_log2"] = max(tune["medium_log2"], tune["tile_log2"] - 4)
+        check_case(l, f, n, B, tune=tune)
+
+
+def test_invalid_tuning_rejected():
+    from paper_1111_3297_amd import api, _lib
+    S, c = api.alloc(5, 4)
+    with pytest.raises(_lib.SieveError):
+        api.Context().sieve(5, 0, 4, 100, S, c, tune={"tile_log2": 17})
+
+
+def test_multi_chunk_and_bucket_path():
+    # small bins force several bucket-fill chunks per launch and many large primes
+    t = {"tile_log2": 13, "medium_log2": 9, "wave_log2": 6, "bins_log2": 8, "groups": 96}
+    check_case(13, (10**12) >> 14, 1 << 10, 10**6, tune=t)   # 2^23 bits, 4 chunks
+    check_case(15, (10**15) >> 16, 1 << 8, 2 * 10**6, tune={"tile_log2": 15, "medium_log2": 11, "bins_log2": 8})
+
+
+def test_prime_table_matches_oracle():
+    import torch
+    from paper_1111_3297_amd import api
+    for B in [3, 5, 13, 17, 1000, 65535, 65536, 65537, 10**6, 2**24 + 17, 10**8 + 7]:
+        say("prime table B=%d" % B)
+        pr = api.Primes(B)
+        got = pr.to_tensor().cpu().numpy().view(np.uint32)
+        torch.cuda.synchronize()
+        want = O.odd_primes(B)
+        assert pr.count == len(want), B
+        assert np.array_equal(got, want), B
+        pr.close()
+
+
+def test_shared_table_and_contexts_on_two_streams():
+    import torch
+    from paper_1111_3297_amd import api
+    pr = api.Primes(10**7)
+    jobs = [(16, (10**13) >> 17, 64, 10**7 - 1), (17, (10**13) >> 18, 32, 3 * 10**6)]
+    outs = []
+    ctxs = [api.Context(), api.Context()]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for (l, f, n, B), ctx, st in zip(jobs, ctxs, streams):
+        say("two-stream job", l, f, n, B)
+        S, c = api.alloc(l, n)
+        with torch.cuda.stream(st):
+            ctx.sieve(l, f, n, B, S, c, primes=pr, stream=st)
+        outs.append((S, c))
+    torch.cuda.synchronize()
+    for (l, f, n, B), (S, c) in zip(jobs, outs):
+        So, co = O.sieve(l, f, n, B)
+        assert first_diff(S.cpu().numpy().view(np.uint32), So) is None
+        assert np.array_equal(c.cpu().numpy().view(np.uint32), co)
+    for ctx in ctxs:
+        ctx.check_device_errors()
+
+
+def test_bucket_contents_match_corollary_1():
+    # Corollary 1 / Theorem 1 (Section 2.3): every hit of every large prime in the
+    # chunk appears exactly once, in the bucket of its bin, with its in-bin offset.
+    from paper_1111_3297_amd import api
+    l, f, n, B = 13, (10**10) >> 14, 256, 200003
+    tune = {"tile_log2": 13, "medium_log2": 10, "wave_log2": 6, "bins_log2": 8, "groups": 64}
+    say("bucket dump", l, f, n, B)
+    d = api.debug_buckets(l, f, n, B, tune=tune)
+    b, cb = d["bin_log2"], d["chunk_bits"]
+    F = f << l
+    primes = [int(p) for p in O.odd_primes(B) if p >= (1 << 10)]
+    assert d["nlarge"] == len(primes)
+    want = [[] for _ in range(len(d["bin_start"]) - 1)]
+    for p in primes:
+        q = ((p - 1) // 2 - F) % p
+        j = q
+        gsq = (p * p - 1) // 2
+        if gsq > F + j:
+            j = gsq - F
+        while j < cb:
+            want[j >> b].append(j & ((1 << b) - 1))
+            j += p
+    bs = d["bin_start"]
+    for k in range(len(want)):
+        got = sorted(int(x) for x in d["entries"][bs[k]:bs[k + 1]])
+        assert got == sorted(want[k]), k
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip("golden file %s not generated" % name)
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("name", ["interval_1e12", "interval_1e12_b6", "interval_2p60"])
+def test_full_size_against_oracle_golden(name):
+    g = _golden(name)
+    say("full size", name, g["l"], g["f"], g["n"], g["B"])
+    S, c = gpu_sieve(g["l"], g["f"], g["n"], g["B"])
+    assert [int(x) for x in c] == g["counts"]
+    assert sha256_words(S) == g["S_sha256"]
