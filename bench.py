@@ -1,0 +1,205 @@
+"""Benchmark: sieved numbers per second of the segmented odd-only sieve on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload interval_1e12]
+
+A step is one full sieve_init call on the workload: device prime generation up to
+B, first offsets, the large-prime bucket fill (when B reaches the bucket range),
+every LDS tile (pattern, medium primes, bucket drain, write-out with popcounts).
+Inputs are interval parameters; outputs land in HBM.  The line printed is one
+JSON object; see the DESIGN notes for the meaning of the roofline and baseline.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X figures used for the roofline ("Roofline").
+CUS, CLOCK_HZ = 256, 2.4e9
+LDS_PEAK_OPS = CUS * CLOCK_HZ * 32          # one 32-bit LDS access per bank per clock, 32 banks
+HBM_PEAK = 8.0e12                           # bytes/s
+
+
+def marks_algorithmic(primes, u, v):
+    """Bit-sets the tile kernel must perform: for every prime 17 <= p <= B, the odd
+    multiples of p in [max(u, p^2), v] (the primes 3..13 come from the pattern)."""
+    import numpy as np
+    p = primes[primes >= 17].astype(np.float64)
+    lo = np.maximum(float(u), p * p)
+    # odd multiples m*p with lo <= m*p <= v: m odd in [ceil(lo/p), floor(v/p)]
+    m0 = np.ceil(lo / p)
+    m0 = m0 + (1 - np.mod(m0, 2))
+    m1 = np.floor(v / p)
+    m1 = m1 - (1 - np.mod(m1, 2))
+    cnt = np.where(m1 >= m0, (m1 - m0) / 2 + 1, 0)
+    return float(cnt.sum())
+
+
+def large_hits(primes, u, v, med_lim):
+    import numpy as np
+    p = primes[primes >= med_lim].astype(np.float64)
+    if p.size == 0:
+        return 0.0
+    lo = np.maximum(float(u), p * p)
+    m0 = np.ceil(lo / p)
+    m0 = m0 + (1 - np.mod(m0, 2))
+    m1 = np.floor(v / p)
+    m1 = m1 - (1 - np.mod(m1, 2))
+    return float(np.where(m1 >= m0, (m1 - m0) / 2 + 1, 0).sum())
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_1111_3297_amd/csrc/kernels.inc", "paper_1111_3297_amd/csrc/sieve.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, kernel):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(l, f, n, B, budget_s=12.0):
+    """The CPU oracle (single-threaded plain C) on a bounded prefix of the workload."""
+    from oracle import oracle as O
+    O.build()
+    # calibrate on a small prefix, then run a prefix sized to the budget
+    n0 = max(1, min(n, 16))
+    t = time.perf_counter()
+    O.count_total(l, f, n0, B)
+    dt0 = time.perf_counter() - t
+    ns = max(n0, min(n, int(n0 * budget_s / max(dt0, 1e-3))))
+    t = time.perf_counter()
+    O.count_total(l, f, ns, B)
+    dt = time.perf_counter() - t
+    numbers = ns * (1 << (l + 1))
+    return {"value": numbers / dt, "unit": "numbers/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d segments (%d numbers) of the same interval and bound, %.1f s"
+                      % (ns, n, numbers, dt)}
+
+
+def run_plain(name, steps, warmup, check=True):
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api, workloads
+    l, f, n, B = workloads.plain_configs()[name]
+    u, v = workloads.interval(l, f, n)
+    S, c = api.alloc(l, n)
+    ctx = api.Context.default()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        api.sieve_init(l, f, n, B, S, c)
+    torch.cuda.synchronize()
+    ctx.kernel_times()                     # drop anything recorded so far
+    ctx.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        api.sieve_init(l, f, n, B, S, c)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    step_ms = sum(lat) / len(lat)
+    numbers = v - u + 1
+    out = {"name": name, "l": l, "f": f, "n": n, "B": B, "u": u, "v": v,
+           "ms_per_step": step_ms, "wall_ms_per_step": 1e3 * wall / steps,
+           "numbers_per_s": numbers / (step_ms * 1e-3),
+           "p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+           "kernels": {k: {"total_ms": ms / steps, "launches_per_step": nl / steps} for k, (ms, nl) in kt.items()}}
+    if check:
+        gpath = os.path.join(ROOT, "tests", "golden", name + ".json")
+        if os.path.exists(gpath):
+            with open(gpath) as fh:
+                g = json.load(fh)
+            Sh = S.cpu().numpy().view(np.uint32)
+            ch = c.cpu().numpy().view(np.uint32)
+            out["bit_exact"] = bool(hashlib.sha256(Sh.tobytes()).hexdigest() == g["S_sha256"]
+                                    and [int(x) for x in ch] == g["counts"])
+        else:
+            out["bit_exact"] = None
+    pr = api.Primes(B)
+    out["_primes"] = pr.to_tensor().cpu().numpy().view(np.uint32)
+    torch.cuda.synchronize()
+    pr.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="interval_1e12")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--also", default="interval_2p60", help="comma list of extra plain workloads to report")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design of a sharded run is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    main_rec = run_plain(args.workload, args.steps, args.warmup)
+    primes = main_rec.pop("_primes")
+    u, v = main_rec["u"], main_rec["v"]
+    marks = marks_algorithmic(primes, u, v)
+    kt = main_rec["kernels"].get("k_tile", {"total_ms": float("nan"), "launches_per_step": 1})
+    per_launch_ms = kt["total_ms"] / kt["launches_per_step"]
+    marks_per_launch = marks / kt["launches_per_step"]
+    achieved = marks_per_launch / (per_launch_ms * 1e-3)
+    traffic = traffic_from_profile(args.workload, "k_tile")
+    roof = {"bound": "lds", "kernel": "k_tile", "achieved": achieved / 1e9, "peak": LDS_PEAK_OPS / 1e9,
+            "unit": "Gmarks/s", "frac": achieved / LDS_PEAK_OPS, "traffic": traffic,
+            "per_launch": {"marks": marks_per_launch, "avg_ms": per_launch_ms,
+                           "launches_per_step": kt["launches_per_step"]}}
+    also = {}
+    for name in [x for x in args.also.split(",") if x and x != "none"]:
+        rec = run_plain(name, max(3, args.steps // 4), 2)
+        pr = rec.pop("_primes")
+        rec["large_prime_hits"] = large_hits(pr, rec["u"], rec["v"], 1 << 20)
+        also[name] = rec
+    out = {
+        "metric": "sieved numbers/sec at 1 GPU (batched vs plain, bit-exact); p99 latency",
+        "value": main_rec["numbers_per_s"], "unit": "numbers/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_rec["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "%s: l=%d f=%d n=%d B=%d (u=%d, v=%d; 2^33 numbers centred at 1e12, plain sieve)"
+                   % (args.workload, main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"], u, v),
+                   "mode": "plain (one sieve_init per step, prime generation included)"},
+        "p50_ms": main_rec["p50_ms"], "p99_ms": main_rec["p99_ms"],
+        "bit_exact": main_rec.get("bit_exact"),
+        "roofline": roof,
+        "kernels_ms_per_step": {k: round(x["total_ms"], 4) for k, x in main_rec["kernels"].items()},
+        "also": {k: {kk: vv for kk, vv in r.items() if kk in ("numbers_per_s", "ms_per_step", "p50_ms", "p99_ms",
+                                                               "bit_exact", "B", "large_prime_hits")}
+                 | {"kernels_ms_per_step": {kk: round(x["total_ms"], 4) for kk, x in r["kernels"].items()}}
+                 for k, r in also.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

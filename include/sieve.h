@@ -62,11 +62,21 @@ typedef enum {
  *   medium_log2 primes below 2^medium_log2 are sieved per tile in LDS (Section
  *               2.1 "medium primes"); primes at or above it take the bucket path
  *               (Sections 2.2-2.5).  tile_log2-4 .. tile_log2+1.  Default tile_log2.
- *   wave_log2   primes below 2^wave_log2 are sieved by a whole wavefront each,
- *               larger medium primes by one lane each (the GPU form of the
- *               per-hit-count grouping of Section 3.2.2).  Default tile_log2-6.
+ *   wave_log2   medium primes below 2^wave_log2 are sieved by a whole wavefront
+ *               each, those below 2^wheel_log2 by eight lanes each (one per
+ *               residue of the 3-5 wheel, Section 3.2.1), the rest by one lane
+ *               each with every hit: the GPU form of the per-hit-count grouping
+ *               of Section 3.2.2.  9 <= wave_log2 <= wheel_log2 <= medium_log2.
+ *               Defaults 9 and min(tile_log2-7, medium_log2) (at least 9).
  *   bins_log2   log2 of the number of large-prime buckets per chunk, 8..15.
- *   groups      workgroups of the bucket-fill kernels, 64..2048. Default 512.
+ *   groups      workgroups of the bucket-fill kernels, 64..2048 (rounded down to
+ *               a multiple of ranges).
+ *   ranges      the buckets of a chunk are split into this many ranges (1, 2, 4
+ *               or 8; default 8) and workgroup g fills range g mod ranges, so the
+ *               workgroups of one XCD append to one range only.
+ *   bin_log2    log2 of one bucket's width in bits, min(tile_log2,16)..tile_log2.
+ *               Up to 16 a hit is stored as a 16-bit in-bucket offset, above 16
+ *               as a 32-bit one.
  */
 typedef struct {
     uint32_t tile_log2;
@@ -74,6 +84,9 @@ typedef struct {
     uint32_t wave_log2;
     uint32_t bins_log2;
     uint32_t groups;
+    uint32_t bin_log2;
+    uint32_t wheel_log2;
+    uint32_t ranges;
     uint32_t reserved[3];
 } sieve_tune;
 
@@ -166,12 +179,12 @@ int sieve_copy_calibration(const void *src_dev, void *dst_dev, uint64_t nbytes, 
 /* --- inspection (tests) ---
  * Runs the offset and bucket-fill kernels for the first chunk of (l, f, n, B) and
  * copies the bucket layout to host memory: bin_start (nbins+1 entries) and the
- * 16-bit in-bin offsets of every large-prime hit (entries, up to cap).  Returns
+ * in-bin offsets of every large-prime hit, widened to 32 bits (entries, up to cap).  Returns
  * the number of bins in *nbins, the bin width log2 in *bin_log2, the number of
  * bits covered in *chunk_bits and the number of large primes in *nlarge.
  * Synchronises. */
 int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune *tune,
-                        uint32_t *bin_start_host, uint32_t bin_cap, uint16_t *entries_host,
+                        uint32_t *bin_start_host, uint32_t bin_cap, uint32_t *entries_host,
                         uint64_t entry_cap, uint32_t *nbins, uint32_t *bin_log2,
                         uint64_t *chunk_bits, uint64_t *nlarge, uint64_t *nentries);
 

@@ -58,15 +58,27 @@ def sieve_init(l, f, n, B, S, counts, stream=None):
 class Context:
     """An explicit library context (include/sieve.h: sieve_ctx_*)."""
 
-    def __init__(self):
-        h = ctypes.c_void_p()
-        L.check(L.load().sieve_ctx_create(ctypes.byref(h)), "sieve_ctx_create")
+    def __init__(self, _handle=None):
+        self._owned = _handle is None
+        if _handle is None:
+            h = ctypes.c_void_p()
+            L.check(L.load().sieve_ctx_create(ctypes.byref(h)), "sieve_ctx_create")
+        else:
+            h = _handle
         self.h = h
 
+    @classmethod
+    def default(cls):
+        """The context sieve_init uses on the current device (not destroyed by close)."""
+        h = L.load().sieve_default_ctx()
+        if not h:
+            raise L.SieveError(-5, "sieve_default_ctx")
+        return cls(_handle=ctypes.c_void_p(h))
+
     def close(self):
-        if self.h:
+        if self.h and self._owned:
             L.load().sieve_ctx_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -161,7 +173,7 @@ def debug_buckets(l, f, n, B, tune=None, entry_cap=1 << 26):
     nbins, blog, cb, nl, ne = (ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64(),
                                ctypes.c_uint64())
     bins = np.zeros(1 << 16, dtype=np.uint32)
-    ent = np.zeros(entry_cap, dtype=np.uint16)
+    ent = np.zeros(entry_cap, dtype=np.uint32)
     L.check(L.load().sieve_debug_buckets(l, f, n, B, _tune(tune), bins.ctypes.data_as(ctypes.c_void_p), bins.size,
                                          ent.ctypes.data_as(ctypes.c_void_p), entry_cap, ctypes.byref(nbins),
                                          ctypes.byref(blog), ctypes.byref(cb), ctypes.byref(nl), ctypes.byref(ne)),

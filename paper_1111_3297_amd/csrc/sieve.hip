@@ -35,7 +35,7 @@ thread_local int g_last_hip = 0;
 
 constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
 constexpr uint32_t kGenTile = 20;             // tile of the prime generator
-constexpr uint32_t kMagicLimit = 1u << 22;    // Barrett constants for primes below this
+constexpr uint32_t kRanges = 8;               // bucket bin ranges (one per XCD)
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -87,7 +87,7 @@ uint64_t isqrt_u64(uint64_t x) {
 }
 
 struct Resolved {
-  uint32_t L, Mlog, Wlog, binslog, groups;
+  uint32_t L, Mlog, Wlog, Blog, binslog, groups, b, R;
 };
 
 int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
@@ -98,12 +98,18 @@ int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
   if (r->L < 13 || r->L > 20 || r->L > l + 10) return SIEVE_E_ARG;  // per-tile count slots fit LDS
   r->Mlog = t->medium_log2 ? t->medium_log2 : r->L;
   if (r->Mlog + 4 < r->L || r->Mlog > r->L + 1) return SIEVE_E_ARG;
-  r->Wlog = t->wave_log2 ? t->wave_log2 : r->L - 6;
-  if (r->Wlog < 5 || r->Wlog > r->Mlog) return SIEVE_E_ARG;
-  r->binslog = t->bins_log2 ? t->bins_log2 : 14;
+  r->Wlog = t->wave_log2 ? t->wave_log2 : 9;
+  r->Blog = t->wheel_log2 ? t->wheel_log2 : std::max<uint32_t>(r->Wlog, std::min<uint32_t>(r->L - 7, r->Mlog));
+  if (r->Wlog < 9 || r->Wlog > r->Blog || r->Blog > r->Mlog) return SIEVE_E_ARG;
+  r->b = t->bin_log2 ? t->bin_log2 : r->L;
+  if (r->b < std::min<uint32_t>(r->L, 16) || r->b > r->L) return SIEVE_E_ARG;
+  r->binslog = t->bins_log2 ? t->bins_log2 : std::min<uint32_t>(15, 31 - r->b);
   if (r->binslog < 8 || r->binslog > 15) return SIEVE_E_ARG;
-  r->groups = t->groups ? t->groups : 512;
+  r->R = t->ranges ? t->ranges : kRanges;
+  if (r->R != 1 && r->R != 2 && r->R != 4 && r->R != 8) return SIEVE_E_ARG;
+  r->groups = t->groups ? t->groups : 256;
   if (r->groups < 64 || r->groups > 2048) return SIEVE_E_ARG;
+  r->groups -= r->groups % r->R;
   return SIEVE_OK;
 }
 
@@ -124,7 +130,7 @@ struct sieve_primes {
   int device = 0;
   uint64_t B = 0;
   uint64_t count = 0;
-  DevBuf P, M, cnt;
+  DevBuf P, cnt;
 };
 
 struct KernelTime {
@@ -140,6 +146,12 @@ struct sieve_ctx {
   hipEvent_t done = nullptr;
   // scratch
   DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk;
+  // batch scratch and the host copies of its tables (kept until the next call)
+  DevBuf b_req, b_blk, b_rd, b_blk2rd, b_seg0, b_tcnt, b_queue;
+  std::vector<sv::BatchReq> h_req;
+  std::vector<uint2> h_blk;
+  std::vector<sv::RangeDesc> h_rd;
+  std::vector<uint32_t> h_blk2rd, h_seg0;
   DevBuf pat[32];
   uint32_t pat_words[32] = {0};
   sieve_primes own;  // table built by sieve_init / sieve_ctx_sieve
@@ -155,7 +167,7 @@ struct sieve_ctx {
 sieve_ctx::~sieve_ctx() {
   if (has_last) (void)hipStreamSynchronize(last_stream);
   DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk,
-                    &own.P, &own.M, &own.cnt};
+                    &b_req, &b_blk, &b_rd, &b_blk2rd, &b_seg0, &b_tcnt, &b_queue, &own.P, &own.cnt};
   for (DevBuf* b : bufs) b->release();
   for (auto& b : pat) b.release();
   for (auto& e : ev_pool) (void)hipEventDestroy(e);
@@ -214,10 +226,12 @@ int set_lds_limits() {
   static int rc = SIEVE_OK;
   std::call_once(once, [] {
     const int lim = 160 * 1024;
-    if (hipFuncSetAttribute((const void*)sv::k_tile, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-        hipFuncSetAttribute((const void*)sv::k_bucket_count, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-        hipFuncSetAttribute((const void*)sv::k_bucket_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
-      rc = SIEVE_E_HIP;
+    const void* fns[] = {(const void*)sv::k_bucket_count, (const void*)sv::k_bucket_scatter<uint16_t>,
+                         (const void*)sv::k_bucket_scatter<uint32_t>, (const void*)sv::k_bucket_count_batch,
+                         (const void*)sv::k_bucket_scatter_batch<uint16_t>,
+                         (const void*)sv::k_bucket_scatter_batch<uint32_t>};
+    for (const void* f : fns)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) rc = SIEVE_E_HIP;
   });
   return rc;
 }
@@ -245,16 +259,34 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
   return SIEVE_OK;
 }
 
-size_t tile_lds_bytes(uint32_t L, uint32_t l, uint32_t patw) {
-  uint32_t nseg = (L >= l) ? (1u << (L - l)) : 1u;
-  return ((size_t)(1u << (L - 5)) + patw + nseg + 1) * 4;
+// Launches the tile kernel instantiated for tile size 2^L and entry type E.
+template <typename E>
+void launch_tile(uint32_t L, uint32_t ntiles, hipStream_t s, const sv::TileArgs& ta) {
+  switch (L) {
+    case 13: sv::k_tile<E, 13><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 14: sv::k_tile<E, 14><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 15: sv::k_tile<E, 15><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 16: sv::k_tile<E, 16><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 17: sv::k_tile<E, 17><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 18: sv::k_tile<E, 18><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 19: sv::k_tile<E, 19><<<ntiles, 1024, 0, s>>>(ta); break;
+    default: sv::k_tile<E, 20><<<ntiles, 1024, 0, s>>>(ta); break;
+  }
+}
+
+// Device error word: allocated and cleared once per context.
+int ensure_err(sieve_ctx* c, hipStream_t s) {
+  if (c->err.p) return SIEVE_OK;
+  STCHK(c->err.ensure(64));
+  sv::k_fill_u32<<<1, 64, 0, s>>>(c->err.as<uint32_t>(), 16, 0);
+  HIPCHK(hipGetLastError());
+  return SIEVE_OK;
 }
 
 // Builds the odd primes 3 <= p <= B into pr (device count in pr->cnt).
 int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
   const uint64_t cap = pi_upper(B) + 16;
   STCHK(pr->P.ensure(cap * 4));
-  STCHK(pr->M.ensure(std::min<uint64_t>(cap, pi_upper(kMagicLimit)) * 4));
   STCHK(pr->cnt.ensure(16));
   uint32_t* P = pr->P.as<uint32_t>();
   uint32_t* cnt = pr->cnt.as<uint32_t>();
@@ -268,14 +300,10 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     uint32_t* base_cnt = base + pi_upper(65536);
     STCHK(launch(c, "k_base_primes", s, [&] { sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)rb, base, base_cnt); }));
     const uint32_t nbase_ub = (uint32_t)pi_upper(65536);
-    STCHK(pr->M.ensure(std::max<uint64_t>(pr->M.bytes, (uint64_t)nbase_ub * 4)));
-    STCHK(launch(c, "k_magic", s, [&] {
-      sv::k_magic<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, base_cnt, pr->M.as<uint32_t>(), nbase_ub);
-    }));
     STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
     sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
     STCHK(launch(c, "k_plan", s, [&] {
-      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, 1ull << (kGenTile - 6), 1ull << 17, gplan);
+      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, 1ull << 9, 1ull << 16, 1ull << 17, nbase_ub, gplan);
     }));
     // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
     // 2^15-bit count segments (the extra bits are masked off by the compaction)
@@ -291,9 +319,9 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     uint32_t* gS = c->gen_S.as<uint32_t>();
     uint32_t* gblk = gS + nwords;
     uint32_t* gcounts = gblk + nblk + 32;
-    STCHK(c->Q0.ensure(pi_upper(65536) * 4));
+    STCHK(c->Q0.ensure(pi_upper(65536) * 8));
     STCHK(launch(c, "k_offsets", s, [&] {
-      sv::k_offsets<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, gplan, 0, gbits, c->Q0.as<uint32_t>(), nullptr);
+      sv::k_offsets<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, gplan, 0, gbits, c->Q0.as<uint2>(), nullptr);
     }));
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, rb, s, &pat, &per, &patw, &pmask));
@@ -301,34 +329,43 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     memset(&ta, 0, sizeof ta);
     ta.G0 = 0; ta.lbits = (uint32_t)gbits; ta.t0 = 0; ta.L = L; ta.l = gl;
     ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = 0; ta.per_tile = (uint32_t)((1ull << L) % per);
-    ta.fixmask = pmask; ta.P = base; ta.M = pr->M.as<uint32_t>(); ta.Q0 = c->Q0.as<uint32_t>();
+    ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
     ta.plan = gplan; ta.psq = 1; ta.has_large = 0; ta.b = 16;
     ta.S = gS; ta.counts = gcounts; ta.count_atomic = 0;
-    STCHK(launch(c, "k_tile[gen]", s, [&] {
-      sv::k_tile<<<ntiles, 1024, tile_lds_bytes(L, gl, patw), s>>>(ta);
-    }));
+    STCHK(launch(c, "k_tile[gen]", s, [&] { launch_tile<uint16_t>(L, ntiles, s, ta); }));
     STCHK(launch(c, "k_compact_count", s, [&] {
       sv::k_compact_count<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk);
     }));
-    STCHK(launch(c, "k_scan_small", s, [&] { sv::k_scan_small<<<1, 1024, 0, s>>>(gblk, nblk, cnt); }));
+    STCHK(ensure_err(c, s));
+    STCHK(launch(c, "k_scan_small", s, [&] { sv::k_scan_small<<<1, 1024, 0, s>>>(gblk, nblk, cnt, (uint32_t)cap); }));
     STCHK(launch(c, "k_compact_write", s, [&] {
-      sv::k_compact_write<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk, P);
+      sv::k_compact_write<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk, P, (uint32_t)cap, c->err.as<uint32_t>());
     }));
   }
-  const uint64_t mlim = std::min<uint64_t>(cap, pi_upper(kMagicLimit));
-  STCHK(launch(c, "k_magic", s, [&] {
-    sv::k_magic<<<(uint32_t)((mlim + 255) / 256), 256, 0, s>>>(P, cnt, pr->M.as<uint32_t>(), (uint32_t)mlim);
-  }));
   pr->B = B;
   return SIEVE_OK;
 }
 
-// Device error word: allocated and cleared once per context.
-int ensure_err(sieve_ctx* c, hipStream_t s) {
-  if (c->err.p) return SIEVE_OK;
-  STCHK(c->err.ensure(64));
-  sv::k_fill_u32<<<1, 64, 0, s>>>(c->err.as<uint32_t>(), 16, 0);
-  HIPCHK(hipGetLastError());
+// One bucket fill (counting sort of a chunk's large-prime hits by bin).
+int bucket_fill(sieve_ctx* c, const sv::BucketArgs& ba, uint32_t G, uint32_t esz, uint32_t cap, hipStream_t s) {
+  const uint32_t nbins = ba.nbins, rbins = ba.rbins;
+  const size_t hl = (size_t)rbins * 4;
+  uint32_t* HG = c->HG.as<uint32_t>();
+  uint32_t* bstart = c->bstart.as<uint32_t>();
+  uint32_t* tot = bstart + nbins + 1;
+  const uint32_t gb = (nbins + 255) / 256;
+  STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count<<<G, 1024, hl, s>>>(ba, HG); }));
+  STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_total<<<gb, 256, 0, s>>>(HG, G, ba.R, rbins, nbins, tot); }));
+  STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, nbins, bstart); }));
+  STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_colprefix<<<gb, 256, 0, s>>>(HG, G, ba.R, rbins, nbins, bstart); }));
+  if (esz == 2)
+    STCHK(launch(c, "k_bucket_scatter", s, [&] {
+      sv::k_bucket_scatter<uint16_t><<<G, 1024, hl, s>>>(ba, HG, c->bucket.as<uint16_t>(), cap, c->err.as<uint32_t>());
+    }));
+  else
+    STCHK(launch(c, "k_bucket_scatter", s, [&] {
+      sv::k_bucket_scatter<uint32_t><<<G, 1024, hl, s>>>(ba, HG, c->bucket.as<uint32_t>(), cap, c->err.as<uint32_t>());
+    }));
   return SIEVE_OK;
 }
 
@@ -336,33 +373,33 @@ int ensure_err(sieve_ctx* c, hipStream_t s) {
 int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint64_t NB, uint64_t B,
               uint32_t* S, uint32_t* counts, const Resolved& R, hipStream_t s) {
   const uint32_t L = R.L;
-  const uint64_t wave_lim = 1ull << R.Wlog, med_lim = 1ull << R.Mlog;
+  const uint64_t wave_lim = 1ull << R.Wlog, wheel_lim = 1ull << R.Blog, med_lim = 1ull << R.Mlog;
   const uint64_t tab_ub = std::min<uint64_t>(pi_upper(B), pi_upper(pr->B));
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
-    sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, wave_lim, med_lim, plan);
+    sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, wave_lim, wheel_lim, med_lim,
+                               (uint32_t)tab_ub, plan);
   }));
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
-  STCHK(c->Q0.ensure(med_ub * 4 + 64));
+  STCHK(c->Q0.ensure(med_ub * 8 + 64));
   const bool large = B >= med_lim;
   const uint64_t nL_ub = large ? tab_ub : 0;
-  if (large) STCHK(c->OFF.ensure(nL_ub * 4 + 64));
+  if (large) STCHK(c->OFF.ensure(2 * nL_ub * 4 + 64));           // in / out halves
   const uint32_t* pat; uint32_t per, patw, pmask;
   STCHK(get_pattern(c, B, s, &pat, &per, &patw, &pmask));
-  const uint32_t b = std::min<uint32_t>(L, 16);
+  const uint32_t b = R.b;
+  const uint32_t esz = b <= 16 ? 2 : 4;                        // bytes per bucket entry
   const uint32_t G = R.groups;
-  const uint64_t chunk_max = (1ull << R.binslog) << b;        // bits per bucket fill
-  const uint32_t splits = (G + 15) / 16;
+  const uint64_t chunk_max = std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits);  // bits per bucket fill
   if (large) {
-    STCHK(c->HG.ensure((size_t)G << R.binslog << 2));
-    STCHK(c->PS.ensure((size_t)splits << R.binslog << 2));
-    STCHK(c->bstart.ensure(((1ull << R.binslog) + 1) * 4));
+    STCHK(c->HG.ensure((size_t)G * (((1ull << R.binslog) + R.R - 1) / R.R) * 4));
+    STCHK(c->bstart.ensure(((2ull << R.binslog) + 2) * 4));   // bin_start, then bin totals
     const uint64_t cb = std::min<uint64_t>(chunk_max, NB);
     const double rs = recip_sum_upper((double)med_lim, (double)B);
     const uint64_t cap = (uint64_t)(1.02 * rs * (double)cb) + nL_ub + 4096;
     if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
-    STCHK(c->bucket.ensure(cap * 2));
+    STCHK(c->bucket.ensure(cap * esz));
   }
   STCHK(ensure_err(c, s));
   const bool count_atomic = L < l;
@@ -377,8 +414,9 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     const uint64_t off_ub = tab_ub;  // grid over primes >= 17
     STCHK(launch(c, "k_offsets", s, [&] {
       sv::k_offsets<<<(uint32_t)((off_ub + 255) / 256), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, lbits,
-                                                                     c->Q0.as<uint32_t>(), large ? c->OFF.as<uint32_t>() : nullptr);
+                                                                     c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr);
     }));
+    uint32_t off_cur = 0;  // which half of OFF holds the offsets of the current chunk
     const uint64_t psq = isqrt_u64(2 * G0 + 1);
     for (uint64_t cs = 0; cs < lbits; cs += chunk_max) {
       const uint64_t cbits = std::min<uint64_t>(chunk_max, lbits - cs);
@@ -388,34 +426,27 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       const uint64_t cap = (uint64_t)(1.02 * rs * (double)std::min<uint64_t>(chunk_max, NB)) + nL_ub + 4096;
       if (large) {
         sv::BucketArgs ba;
-        ba.P = pr->P.as<uint32_t>(); ba.plan = plan; ba.OFF = c->OFF.as<uint32_t>();
+        ba.P = pr->P.as<uint32_t>(); ba.plan = plan;
+        ba.OFF_in = c->OFF.as<uint32_t>() + (size_t)off_cur * nL_ub;
+        ba.OFF_out = c->OFF.as<uint32_t>() + (size_t)(1 - off_cur) * nL_ub;
         ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins;
-        const size_t hl = (size_t)nbins * 4;
-        STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count<<<G, 1024, hl, s>>>(ba, c->HG.as<uint32_t>()); }));
-        STCHK(launch(c, "k_bin_colsum", s, [&] {
-          sv::k_bin_colsum<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
-        }));
-        STCHK(launch(c, "k_bin_scan", s, [&] {
-          sv::k_bin_scan<<<1, 1024, 0, s>>>(c->PS.as<uint32_t>(), splits, nbins, c->bstart.as<uint32_t>());
-        }));
-        STCHK(launch(c, "k_bin_colprefix", s, [&] {
-          sv::k_bin_colprefix<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
-        }));
-        STCHK(launch(c, "k_bucket_scatter", s, [&] {
-          sv::k_bucket_scatter<<<G, 1024, hl, s>>>(ba, c->HG.as<uint32_t>(), c->bucket.as<uint16_t>(), (uint32_t)cap,
-                                                   c->err.as<uint32_t>());
-        }));
+        ba.R = R.R; ba.rbins = (nbins + R.R - 1) / R.R;
+        STCHK(bucket_fill(c, ba, G, esz, (uint32_t)cap, s));
+        off_cur ^= 1u;
       }
       sv::TileArgs ta;
       memset(&ta, 0, sizeof ta);
       ta.G0 = G0; ta.lbits = (uint32_t)lbits; ta.t0 = (uint32_t)(cs >> L); ta.L = L; ta.l = l;
       ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
-      ta.fixmask = pmask; ta.P = pr->P.as<uint32_t>(); ta.M = pr->M.as<uint32_t>(); ta.Q0 = c->Q0.as<uint32_t>();
+      ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
       ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
-      ta.bucket = large ? c->bucket.as<uint16_t>() : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
+      ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
       ta.b = b; ta.nbins = nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
       ta.S = S + (ls >> 5); ta.counts = counts + (ls >> l); ta.count_atomic = count_atomic ? 1 : 0;
-      STCHK(launch(c, "k_tile", s, [&] { sv::k_tile<<<ntiles, 1024, tile_lds_bytes(L, l, patw), s>>>(ta); }));
+      if (esz == 2)
+        STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(L, ntiles, s, ta); }));
+      else
+        STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(L, ntiles, s, ta); }));
     }
   }
   return SIEVE_OK;
@@ -516,7 +547,7 @@ int sieve_primes_create(uint64_t B, void* stream, sieve_primes** out) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { g_last_hip = (int)e; rc = SIEVE_E_HIP; }
   }
-  if (rc != SIEVE_OK) { pr->P.release(); pr->M.release(); pr->cnt.release(); delete pr; return rc; }
+  if (rc != SIEVE_OK) { pr->P.release(); pr->cnt.release(); delete pr; return rc; }
   pr->count = cnt;
   pr->device = c->device;
   *out = pr;
@@ -526,7 +557,7 @@ int sieve_primes_create(uint64_t B, void* stream, sieve_primes** out) {
 int sieve_primes_destroy(sieve_primes* pr) {
   if (!pr) return SIEVE_E_ARG;
   (void)hipDeviceSynchronize();
-  pr->P.release(); pr->M.release(); pr->cnt.release();
+  pr->P.release(); pr->cnt.release();
   delete pr;
   return SIEVE_OK;
 }
@@ -636,7 +667,7 @@ int sieve_copy_calibration(const void* src_dev, void* dst_dev, uint64_t nbytes, 
 }
 
 int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune* tune,
-                        uint32_t* bin_start_host, uint32_t bin_cap, uint16_t* entries_host, uint64_t entry_cap,
+                        uint32_t* bin_start_host, uint32_t bin_cap, uint32_t* entries_host, uint64_t entry_cap,
                         uint32_t* nbins_out, uint32_t* bin_log2, uint64_t* chunk_bits, uint64_t* nlarge,
                         uint64_t* nentries) {
   uint64_t F, NB;
@@ -644,60 +675,60 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   Resolved R;
   STCHK(resolve_tune(l, tune, &R));
   if (!bin_start_host || !nbins_out) return SIEVE_E_ARG;
+  const uint64_t med_lim = 1ull << R.Mlog;
+  if (B < med_lim) return SIEVE_E_ARG;  // no large primes
   sieve_ctx* c = sieve_default_ctx();
   if (!c) return SIEVE_E_HIP;
   std::lock_guard<std::mutex> g(c->mu);
   hipStream_t s = nullptr;
   STCHK(begin(c, s));
   STCHK(build_primes(c, B, &c->own, s));
-  const uint64_t med_lim = 1ull << R.Mlog;
-  if (B < med_lim) return SIEVE_E_ARG;  // no large primes
   const uint64_t tab_ub = pi_upper(B);
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
-  sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 1ull << R.Wlog, med_lim, plan);
-  STCHK(c->Q0.ensure(tab_ub * 4 + 64));
-  STCHK(c->OFF.ensure(tab_ub * 4 + 64));
+  sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 1ull << R.Wlog, 1ull << R.Blog,
+                             med_lim, (uint32_t)tab_ub, plan);
+  STCHK(c->Q0.ensure(tab_ub * 8 + 64));
+  STCHK(c->OFF.ensure(2 * tab_ub * 4 + 64));
   const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB);
   sv::k_offsets<<<(uint32_t)((tab_ub + 255) / 256), 256, 0, s>>>(c->own.P.as<uint32_t>(), plan, F, lbits,
-                                                                 c->Q0.as<uint32_t>(), c->OFF.as<uint32_t>());
-  const uint32_t b = std::min<uint32_t>(R.L, 16);
-  const uint64_t cbits = std::min<uint64_t>((1ull << R.binslog) << b, lbits);
+                                                                 c->Q0.as<uint2>(), c->OFF.as<uint32_t>());
+  const uint32_t b = R.b, esz = b <= 16 ? 2 : 4;
+  const uint64_t cbits = std::min<uint64_t>(std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits), lbits);
   const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
-  const uint32_t G = R.groups, splits = (G + 15) / 16;
-  STCHK(c->HG.ensure((size_t)G * nbins * 4));
-  STCHK(c->PS.ensure((size_t)splits * nbins * 4));
-  STCHK(c->bstart.ensure((nbins + 1) * 4));
+  const uint32_t G = R.groups;
+  const uint32_t rbins = (nbins + R.R - 1) / R.R;
+  STCHK(c->HG.ensure((size_t)G * rbins * 4));
+  STCHK(c->bstart.ensure((2 * nbins + 2) * 4));
   const double rs = recip_sum_upper((double)med_lim, (double)B);
   const uint64_t cap = (uint64_t)(1.02 * rs * (double)cbits) + tab_ub + 4096;
-  STCHK(c->bucket.ensure(cap * 2));
+  STCHK(c->bucket.ensure(cap * esz));
   STCHK(ensure_err(c, s));
   sv::BucketArgs ba;
-  ba.P = c->own.P.as<uint32_t>(); ba.plan = plan; ba.OFF = c->OFF.as<uint32_t>();
-  ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins;
-  sv::k_bucket_count<<<G, 1024, nbins * 4, s>>>(ba, c->HG.as<uint32_t>());
-  sv::k_bin_colsum<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
-  sv::k_bin_scan<<<1, 1024, 0, s>>>(c->PS.as<uint32_t>(), splits, nbins, c->bstart.as<uint32_t>());
-  sv::k_bin_colprefix<<<dim3((nbins + 255) / 256, splits), 256, 0, s>>>(c->HG.as<uint32_t>(), G, nbins, 16, c->PS.as<uint32_t>());
-  sv::k_bucket_scatter<<<G, 1024, nbins * 4, s>>>(ba, c->HG.as<uint32_t>(), c->bucket.as<uint16_t>(), (uint32_t)cap,
-                                                   c->err.as<uint32_t>());
-  HIPCHK(hipGetLastError());
+  ba.P = c->own.P.as<uint32_t>(); ba.plan = plan;
+  ba.OFF_in = c->OFF.as<uint32_t>(); ba.OFF_out = c->OFF.as<uint32_t>() + tab_ub;
+  ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins; ba.R = R.R; ba.rbins = rbins;
+  STCHK(bucket_fill(c, ba, G, esz, (uint32_t)cap, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<uint32_t> bs(nbins + 1);
   HIPCHK(hipMemcpy(bs.data(), c->bstart.p, (nbins + 1) * 4, hipMemcpyDeviceToHost));
-  uint32_t np_cnt = 0;
   sv::Plan hp;
   HIPCHK(hipMemcpy(&hp, plan, sizeof hp, hipMemcpyDeviceToHost));
-  (void)np_cnt;
-  if (nbins_out) *nbins_out = nbins;
+  *nbins_out = nbins;
   if (bin_log2) *bin_log2 = b;
   if (chunk_bits) *chunk_bits = cbits;
   if (nlarge) *nlarge = hp.np - hp.iM;
   if (nentries) *nentries = bs[nbins];
-  if (bin_start_host) memcpy(bin_start_host, bs.data(), std::min<uint32_t>(bin_cap, nbins + 1) * 4);
+  memcpy(bin_start_host, bs.data(), std::min<uint32_t>(bin_cap, nbins + 1) * 4);
   if (entries_host) {
-    uint64_t ne = std::min<uint64_t>(entry_cap, bs[nbins]);
-    if (ne) HIPCHK(hipMemcpy(entries_host, c->bucket.p, ne * 2, hipMemcpyDeviceToHost));
+    const uint64_t ne = std::min<uint64_t>(std::min<uint64_t>(entry_cap, bs[nbins]), cap);
+    if (esz == 4) {
+      if (ne) HIPCHK(hipMemcpy(entries_host, c->bucket.p, ne * 4, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<uint16_t> tmp(ne);
+      if (ne) HIPCHK(hipMemcpy(tmp.data(), c->bucket.p, ne * 2, hipMemcpyDeviceToHost));
+      for (uint64_t i = 0; i < ne; ++i) entries_host[i] = tmp[i];
+    }
   }
   uint32_t ev = 0;
   HIPCHK(hipMemcpy(&ev, c->err.p, 4, hipMemcpyDeviceToHost));
@@ -709,15 +740,252 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   return end(c, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// One window of a batched request (at most kLaunchBits bits).
+struct Window {
+  uint64_t G0, B;
+  uint32_t lbits;
+  uint32_t* S;
+  uint32_t* counts;
+  double cost;
+};
+
+int batch_windows(const sieve_primes* pr, uint32_t l, const sieve_req* reqs, size_t nreq, const Resolved& R,
+                  std::vector<Window>* out) {
+  out->clear();
+  for (size_t i = 0; i < nreq; ++i) {
+    uint64_t F, NB;
+    STCHK(check_interval(l, reqs[i].f, reqs[i].n, reqs[i].B, &F, &NB));
+    if (reqs[i].B > pr->B) return SIEVE_E_BOUND;
+    if (!reqs[i].S_dev || !reqs[i].counts_dev) return SIEVE_E_ARG;
+    for (uint64_t ws = 0; ws < NB; ws += kLaunchBits) {
+      Window w;
+      w.G0 = F + ws;
+      w.B = reqs[i].B;
+      w.lbits = (uint32_t)std::min<uint64_t>(kLaunchBits, NB - ws);
+      w.S = reqs[i].S_dev + (ws >> 5);
+      w.counts = reqs[i].counts_dev + (ws >> l);
+      // work estimate: per tile one visit per medium prime, plus the marks
+      const double tiles = std::ceil((double)w.lbits / (double)(1u << R.L));
+      const double med = (double)pi_upper(std::min<uint64_t>(w.B, 1ull << R.Mlog));
+      const double lb = std::log(std::log(std::max<double>((double)w.B, 17.0)));
+      w.cost = tiles * med + (double)w.lbits * lb * 0.5;
+      out->push_back(w);
+    }
+  }
+  std::stable_sort(out->begin(), out->end(), [](const Window& a, const Window& b) { return a.cost > b.cost; });
+  return SIEVE_OK;
+}
+
+uint64_t window_cap(const Window& w, uint64_t med_lim) {
+  const double rs = recip_sum_upper((double)med_lim, (double)w.B);
+  return (uint64_t)(1.02 * rs * (double)w.lbits) + pi_upper(w.B) + 4096;
+}
+
+uint32_t tiles_per_cu(uint32_t L) {
+  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1) * 4;
+  return (uint32_t)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / lds));
+}
+
+template <typename E>
+void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::BatchReq* rq, uint32_t nreq, uint32_t nitems,
+                       uint32_t* queue, const void* bucket, const uint32_t* bstart, uint32_t b, uint32_t cap, uint32_t l,
+                       uint32_t* tcnt) {
+#define SV_TB(LL) sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, queue, bucket, bstart, b, cap, l, tcnt)
+  switch (L) {
+    case 13: SV_TB(13); break;
+    case 14: SV_TB(14); break;
+    case 15: SV_TB(15); break;
+    case 16: SV_TB(16); break;
+    case 17: SV_TB(17); break;
+    case 18: SV_TB(18); break;
+    case 19: SV_TB(19); break;
+    default: SV_TB(20); break;
+  }
+#undef SV_TB
+}
+
+// Device scratch (bytes) of a batch with these windows: slabs of offsets,
+// bucket entries, histograms and the per-window tables.
+uint64_t batch_bytes(const std::vector<Window>& W, const Resolved& R, uint32_t l) {
+  const uint64_t med_lim = 1ull << R.Mlog;
+  const uint32_t esz = R.b <= 16 ? 2 : 4;
+  uint64_t qp = 0, off = 0, cap = 0, bins = 0, hg = 0, tiles = 0;
+  for (const Window& w : W) {
+    qp += pi_upper(std::min<uint64_t>(w.B, med_lim)) + 16;
+    off += pi_upper(w.B) + 16;
+    tiles += (w.lbits + (1u << R.L) - 1) >> R.L;
+    if (w.B >= med_lim) {
+      cap += window_cap(w, med_lim);
+      const uint64_t nb = (w.lbits + (1ull << R.b) - 1) >> R.b;
+      bins += nb;
+      hg += nb * 32;  // at most 32 blocks per range
+    }
+  }
+  (void)l;
+  return qp * 8 + off * 4 + cap * esz + bins * 12 + hg * 4 + tiles * 4 + W.size() * sizeof(sv::BatchReq) + 4096;
+}
+
+}  // namespace
+
+extern "C" {
+
 int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_req* reqs, size_t nreq,
                 const sieve_tune* tune, void* stream) {
-  // Interim: requests run back to back on the shared table (replaced by the
-  // persistent batched launch).
   if (!ctx || !pr || (!reqs && nreq)) return SIEVE_E_ARG;
-  for (size_t i = 0; i < nreq; ++i)
-    STCHK(sieve_ctx_sieve_with(ctx, pr, l, reqs[i].f, reqs[i].n, reqs[i].B, reqs[i].S_dev, reqs[i].counts_dev,
-                               tune, stream));
-  return SIEVE_OK;
+  Resolved R;
+  STCHK(resolve_tune(l, tune, &R));
+  std::vector<Window> W;
+  STCHK(batch_windows(pr, l, reqs, nreq, R, &W));
+  if (W.empty()) return SIEVE_OK;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  sieve_ctx* c = ctx;
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(c, s));
+  const uint32_t L = R.L, b = R.b, esz = b <= 16 ? 2 : 4;
+  const uint64_t med_lim = 1ull << R.Mlog;
+  const uint32_t nw = (uint32_t)W.size();
+  // per-window layout
+  c->h_req.assign(nw, sv::BatchReq());
+  c->h_blk.clear();
+  c->h_rd.clear();
+  c->h_blk2rd.clear();
+  c->h_seg0.assign(nw, 0);
+  uint64_t qp_tot = 0, off_tot = 0, cap_tot = 0, hg_tot = 0;
+  uint32_t items = 0, gbins = 0, tcnt = 0, seg_tot = 0, max_rbins = 1;
+  const bool seg_long = L < l;
+  for (uint32_t w = 0; w < nw; ++w) {
+    const Window& X = W[w];
+    sv::BatchReq& q = c->h_req[w];
+    memset(&q, 0, sizeof q);
+    q.G0 = X.G0; q.B = X.B; q.lbits = X.lbits;
+    q.ntiles = (X.lbits + (1u << L) - 1) >> L;
+    q.item0 = items; items += q.ntiles;
+    q.psq = (uint32_t)std::min<uint64_t>(isqrt_u64(2 * X.G0 + 1), 0xFFFFFFFFull);
+    const uint32_t* pat; uint32_t per, patw, pmask;
+    STCHK(get_pattern(c, X.B, s, &pat, &per, &patw, &pmask));
+    q.pat = pat; q.per = per; q.patw = patw; q.per_G0 = (uint32_t)(X.G0 % per);
+    q.per_tile = (uint32_t)((1ull << L) % per); q.fixmask = pmask;
+    q.qp_cap = (uint32_t)(pi_upper(std::min<uint64_t>(X.B, med_lim)) + 16);
+    q.off_cap = (uint32_t)(pi_upper(X.B) + 16);
+    q.QP = reinterpret_cast<uint2*>(qp_tot);       // offsets into the slabs; rebased below
+    q.OFF = reinterpret_cast<uint32_t*>(off_tot);
+    qp_tot += q.qp_cap; off_tot += q.off_cap;
+    q.S = X.S; q.counts = X.counts;
+    q.tcnt_base = tcnt;
+    if (seg_long) tcnt += q.ntiles;
+    c->h_seg0[w] = seg_tot;
+    seg_tot += X.lbits >> l;
+    for (uint32_t k = 0; k * 256u < q.off_cap; ++k) c->h_blk.push_back(make_uint2(w, k));
+    if (X.B >= med_lim) {
+      q.nbins = (X.lbits + (1u << b) - 1) >> b;
+      q.bin_base = gbins;
+      const uint32_t Rw = std::min<uint32_t>(R.R, q.nbins);
+      const uint32_t rbins = (q.nbins + Rw - 1) / Rw;
+      const uint32_t GR = (uint32_t)std::min<uint64_t>(32, std::max<uint64_t>(1, (q.off_cap + 16383) / 16384));
+      for (uint32_t x = 0; x < Rw; ++x) {
+        sv::RangeDesc d;
+        d.req = w; d.kb0 = x * rbins; d.kb1 = std::min(q.nbins, d.kb0 + rbins);
+        if (d.kb0 >= d.kb1) break;
+        d.rbins = rbins; d.block0 = (uint32_t)c->h_blk2rd.size(); d.GR = GR; d.hg = (uint32_t)hg_tot;
+        d.gbin0 = gbins + d.kb0;
+        hg_tot += (uint64_t)GR * rbins;
+        for (uint32_t k = 0; k < GR; ++k) c->h_blk2rd.push_back((uint32_t)c->h_rd.size());
+        c->h_rd.push_back(d);
+      }
+      max_rbins = std::max(max_rbins, rbins);
+      gbins += q.nbins;
+      cap_tot += window_cap(X, med_lim);
+    }
+  }
+  if (cap_tot >= 0xFFFFFFFFull || hg_tot >= 0xFFFFFFFFull || (size_t)max_rbins * 4 > 160 * 1024) return SIEVE_E_NOMEM;
+  // device buffers
+  STCHK(c->Q0.ensure(qp_tot * 8 + 64));
+  STCHK(c->OFF.ensure(off_tot * 4 + 64));
+  STCHK(ensure_err(c, s));
+  for (sv::BatchReq& q : c->h_req) {
+    q.QP = c->Q0.as<uint2>() + reinterpret_cast<uintptr_t>(q.QP);
+    q.OFF = c->OFF.as<uint32_t>() + reinterpret_cast<uintptr_t>(q.OFF);
+  }
+  STCHK(c->b_req.ensure(nw * sizeof(sv::BatchReq)));
+  STCHK(c->b_blk.ensure(c->h_blk.size() * sizeof(uint2)));
+  STCHK(c->b_seg0.ensure(nw * 4));
+  STCHK(c->b_queue.ensure(64));
+  if (seg_long) STCHK(c->b_tcnt.ensure((size_t)tcnt * 4 + 64));
+  HIPCHK(hipMemcpyAsync(c->b_req.p, c->h_req.data(), nw * sizeof(sv::BatchReq), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->b_blk.p, c->h_blk.data(), c->h_blk.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->b_seg0.p, c->h_seg0.data(), nw * 4, hipMemcpyHostToDevice, s));
+  sv::BatchReq* dreq = c->b_req.as<sv::BatchReq>();
+  STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<1, 64, 0, s>>>(c->b_queue.as<uint32_t>(), 16, 0); }));
+  STCHK(launch(c, "k_plan_batch", s, [&] {
+    sv::k_plan_batch<<<(nw + 63) / 64, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), dreq, nw,
+                                                   1ull << R.Wlog, 1ull << R.Blog, med_lim);
+  }));
+  const uint32_t nblk = (uint32_t)c->h_blk.size();
+  STCHK(launch(c, "k_offsets_batch", s, [&] {
+    sv::k_offsets_batch<<<nblk, 256, 0, s>>>(pr->P.as<uint32_t>(), dreq, c->b_blk.as<uint2>());
+  }));
+  const uint32_t nrd = (uint32_t)c->h_rd.size();
+  uint32_t cap32 = 0;
+  if (nrd) {
+    const uint32_t nbb = (uint32_t)c->h_blk2rd.size();
+    STCHK(c->b_rd.ensure(nrd * sizeof(sv::RangeDesc)));
+    STCHK(c->b_blk2rd.ensure(nbb * 4));
+    STCHK(c->HG.ensure(hg_tot * 4 + 64));
+    STCHK(c->bstart.ensure(((size_t)2 * gbins + 2) * 4));
+    STCHK(c->bucket.ensure(cap_tot * esz));
+    HIPCHK(hipMemcpyAsync(c->b_rd.p, c->h_rd.data(), nrd * sizeof(sv::RangeDesc), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->b_blk2rd.p, c->h_blk2rd.data(), nbb * 4, hipMemcpyHostToDevice, s));
+    const sv::RangeDesc* drd = c->b_rd.as<sv::RangeDesc>();
+    const uint32_t* dbr = c->b_blk2rd.as<uint32_t>();
+    uint32_t* HG = c->HG.as<uint32_t>();
+    uint32_t* bst = c->bstart.as<uint32_t>();
+    uint32_t* tot = bst + gbins + 1;
+    const size_t hl = (size_t)max_rbins * 4;
+    cap32 = (uint32_t)cap_tot;
+    STCHK(launch(c, "k_bucket_count", s, [&] {
+      sv::k_bucket_count_batch<<<nbb, 1024, hl, s>>>(pr->P.as<uint32_t>(), dreq, drd, dbr, b, HG);
+    }));
+    STCHK(launch(c, "k_bin_total", s, [&] {
+      sv::k_bin_batch<<<(gbins + 255) / 256, 256, 0, s>>>(HG, drd, nrd, gbins, tot, bst, 0);
+    }));
+    STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, gbins, bst); }));
+    STCHK(launch(c, "k_bin_colprefix", s, [&] {
+      sv::k_bin_batch<<<(gbins + 255) / 256, 256, 0, s>>>(HG, drd, nrd, gbins, tot, bst, 1);
+    }));
+    if (esz == 2)
+      STCHK(launch(c, "k_bucket_scatter", s, [&] {
+        sv::k_bucket_scatter_batch<uint16_t><<<nbb, 1024, hl, s>>>(pr->P.as<uint32_t>(), dreq, drd, dbr, b, HG,
+                                                                  c->bucket.as<uint16_t>(), cap32, c->err.as<uint32_t>());
+      }));
+    else
+      STCHK(launch(c, "k_bucket_scatter", s, [&] {
+        sv::k_bucket_scatter_batch<uint32_t><<<nbb, 1024, hl, s>>>(pr->P.as<uint32_t>(), dreq, drd, dbr, b, HG,
+                                                                  c->bucket.as<uint32_t>(), cap32, c->err.as<uint32_t>());
+      }));
+  }
+  int ncu = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)ncu * tiles_per_cu(L), items);
+  uint32_t* tc = seg_long ? c->b_tcnt.as<uint32_t>() : nullptr;
+  const void* bk = nrd ? c->bucket.p : nullptr;
+  const uint32_t* bsp = nrd ? c->bstart.as<uint32_t>() : nullptr;
+  if (esz == 2)
+    STCHK(launch(c, "k_tile_batch", s, [&] {
+      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
+    }));
+  else
+    STCHK(launch(c, "k_tile_batch", s, [&] {
+      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
+    }));
+  if (seg_long)
+    STCHK(launch(c, "k_counts_batch", s, [&] {
+      sv::k_counts_batch<<<(seg_tot + 255) / 256, 256, 0, s>>>(dreq, nw, c->b_seg0.as<uint32_t>(), seg_tot, tc, l - L);
+    }));
+  return end(c, s);
 }
 
 int sieve_batch_scratch_bytes(const sieve_primes* pr, uint32_t l, const sieve_req* reqs, size_t nreq,
@@ -725,13 +993,11 @@ int sieve_batch_scratch_bytes(const sieve_primes* pr, uint32_t l, const sieve_re
   if (!pr || !bytes || (!reqs && nreq)) return SIEVE_E_ARG;
   Resolved R;
   STCHK(resolve_tune(l, tune, &R));
-  uint64_t tot = 0;
-  for (size_t i = 0; i < nreq; ++i) {
-    const uint64_t NB = reqs[i].n << l;
-    const double rs = recip_sum_upper((double)(1ull << R.Mlog), (double)reqs[i].B);
-    tot += (uint64_t)(1.02 * rs * (double)NB) * 2 + pi_upper(reqs[i].B) * 8;
-  }
-  *bytes = tot;
+  std::vector<sieve_req> rr(reqs, reqs + nreq);
+  for (auto& r : rr) { if (!r.S_dev) r.S_dev = reinterpret_cast<uint32_t*>(16); if (!r.counts_dev) r.counts_dev = reinterpret_cast<uint32_t*>(16); }
+  std::vector<Window> W;
+  STCHK(batch_windows(pr, l, rr.data(), nreq, R, &W));
+  *bytes = batch_bytes(W, R, l);
   return SIEVE_OK;
 }
 

@@ -9,6 +9,8 @@ Workloads (interval parameters of Section 1.2.1):
   interval_1e12    : l=20, n=4096, f=floor((10^12 - 2^32)/2^21), B = isqrt(v)
   interval_1e12_b6 : the same interval with the literal bound B = 10^6 (partial sieve)
   interval_2p60    : l=20, n=4096, f=2^39-2048 (centred at 2^60), B = 2^30
+  batch_1234       : the 256 interval requests of the seeded batch workload
+                     (paper_1111_3297_amd/workloads.py), B = isqrt(v) each
 Run: python tests/golden/make_golden.py [name ...]
 """
 import hashlib
@@ -35,8 +37,30 @@ def workloads():
     }
 
 
+def batch_golden(name="batch_1234"):
+    """The 256-request batch (seed 1234): per request the oracle's zero-bit total and
+    the SHA-256 of its counts and of its table, with B = isqrt(v) per request."""
+    sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+    from paper_1111_3297_amd import workloads as WL
+    out = []
+    t = time.time()
+    for f21, n21 in WL.batch_requests(1234, 256):
+        u, v = O.interval(20, f21, n21)
+        B = math.isqrt(v)
+        S, c = O.sieve(20, f21, n21, B)
+        out.append({"f": f21, "n": n21, "B": B, "total": int(c.sum()),
+                    "counts_sha256": hashlib.sha256(c.astype("<u4").tobytes()).hexdigest(),
+                    "S_sha256": hashlib.sha256(S.tobytes()).hexdigest()})
+    with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        json.dump({"name": name, "l": 20, "requests": out, "oracle_seconds": round(time.time() - t, 1)}, fh)
+    print(name, sum(r["total"] for r in out), round(time.time() - t, 1), "s", flush=True)
+
+
 def main(names):
     W = workloads()
+    if names == ["batch_1234"]:
+        batch_golden()
+        return
     for name in names or list(W):
         l, f, n, B = W[name]
         t = time.time()

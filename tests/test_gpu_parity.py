@@ -54,10 +54,14 @@ def test_near_2_64_partial_sieve():
 def test_random_small_with_tunings():
     rng = random.Random(20111111)
     tunings = [None,
-               {"tile_log2": 13, "medium_log2": 9, "wave_log2": 6, "bins_log2": 8, "groups": 64},
-               {"tile_log2": 14, "medium_log2": 12, "wave_log2": 8, "bins_log2": 9},
-               {"tile_log2": 17, "medium_log2": 14, "wave_log2": 10},
-               {"tile_log2": 15, "medium_log2": 16, "wave_log2": 5, "bins_log2": 10, "groups": 128}]
+               {"tile_log2": 13, "medium_log2": 9, "wave_log2": 9, "bins_log2": 8, "groups": 64},
+               {"tile_log2": 14, "medium_log2": 12, "wave_log2": 9, "wheel_log2": 10, "bins_log2": 9},
+               {"tile_log2": 17, "medium_log2": 14, "wave_log2": 10, "wheel_log2": 12},
+               {"tile_log2": 15, "medium_log2": 16, "wave_log2": 9, "wheel_log2": 9, "bins_log2": 10, "groups": 128},
+               {"tile_log2": 17, "medium_log2": 15, "wave_log2": 9, "bins_log2": 9, "bin_log2": 17},
+               {"tile_log2": 14, "medium_log2": 11, "wave_log2": 9, "bins_log2": 8, "bin_log2": 14},
+               {"tile_log2": 16, "medium_log2": 13, "bins_log2": 10, "bin_log2": 16, "groups": 200, "ranges": 1},
+               {"tile_log2": 15, "medium_log2": 12, "bins_log2": 9, "groups": 100, "ranges": 4}]
     for k in range(40):
         l = rng.choice([5, 7, 11, 13, 15, 16, 17])
         n = rng.randint(1, max(1, (1 << 21) >> l))
@@ -70,9 +74,12 @@ def test_random_small_with_tunings():
         B = max(3, min(B, 2**24))
         tune = tunings[k % len(tunings)]
         if tune is not None and tune["tile_log2"] > l + 10:   # per-tile count slots must fit LDS
-            tune = dict(tune, tile_log2=l + 10, medium_log2=min(tune["medium_log2"], l + 11),
-                        wave_log2=min(tune["wave_log2"], l + 10))
-            tune["medium_log2"] = max(tune["medium_log2"], tune["tile_log2"] - 4)
+            tl = l + 10
+            tune = dict(tune, tile_log2=tl, medium_log2=min(max(tune["medium_log2"], tl - 4), tl + 1))
+            tune["wave_log2"] = 9
+            tune["wheel_log2"] = max(9, min(tune.get("wheel_log2", tl - 4), tune["medium_log2"]))
+            if "bin_log2" in tune:
+                tune["bin_log2"] = tl
         check_case(l, f, n, B, tune=tune)
 
 
@@ -85,9 +92,12 @@ def test_invalid_tuning_rejected():
 
 def test_multi_chunk_and_bucket_path():
     # small bins force several bucket-fill chunks per launch and many large primes
-    t = {"tile_log2": 13, "medium_log2": 9, "wave_log2": 6, "bins_log2": 8, "groups": 96}
+    t = {"tile_log2": 13, "medium_log2": 9, "wave_log2": 9, "bins_log2": 8, "groups": 96}
     check_case(13, (10**12) >> 14, 1 << 10, 10**6, tune=t)   # 2^23 bits, 4 chunks
     check_case(15, (10**15) >> 16, 1 << 8, 2 * 10**6, tune={"tile_log2": 15, "medium_log2": 11, "bins_log2": 8})
+    # 32-bit bucket entries: one bin per tile
+    check_case(17, (10**14) >> 18, 1 << 6, 3 * 10**6,
+               tune={"tile_log2": 17, "medium_log2": 14, "bins_log2": 8, "bin_log2": 17, "groups": 80})
 
 
 def test_prime_table_matches_oracle():
@@ -132,12 +142,19 @@ def test_bucket_contents_match_corollary_1():
     # chunk appears exactly once, in the bucket of its bin, with its in-bin offset.
     from paper_1111_3297_amd import api
     l, f, n, B = 13, (10**10) >> 14, 256, 200003
-    tune = {"tile_log2": 13, "medium_log2": 10, "wave_log2": 6, "bins_log2": 8, "groups": 64}
-    say("bucket dump", l, f, n, B)
+    for tune in ({"tile_log2": 13, "medium_log2": 10, "wave_log2": 9, "bins_log2": 8, "groups": 64, "bin_log2": 13},
+                 {"tile_log2": 17, "medium_log2": 14, "wave_log2": 9, "bins_log2": 8, "groups": 64, "bin_log2": 16},
+                 {"tile_log2": 15, "medium_log2": 11, "wave_log2": 9, "bins_log2": 8, "groups": 64, "bin_log2": 15}):
+        _check_buckets(l, f, n, B, tune)
+
+
+def _check_buckets(l, f, n, B, tune):
+    from paper_1111_3297_amd import api
+    say("bucket dump", l, f, n, B, tune)
     d = api.debug_buckets(l, f, n, B, tune=tune)
     b, cb = d["bin_log2"], d["chunk_bits"]
     F = f << l
-    primes = [int(p) for p in O.odd_primes(B) if p >= (1 << 10)]
+    primes = [int(p) for p in O.odd_primes(B) if p >= (1 << tune["medium_log2"])]
     assert d["nlarge"] == len(primes)
     want = [[] for _ in range(len(d["bin_start"]) - 1)]
     for p in primes:
