@@ -144,6 +144,91 @@ def run_plain(name, steps, warmup, check=True):
     return out
 
 
+def run_batch_bench(steps, log):
+    """The 256-request batch (seed 1234, B = isqrt(v) each): one persistent batched
+    launch per step against looping the plain per-interval sieve."""
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api, autotune, workloads
+    l = 20
+    reqs = []
+    for f21, n21 in workloads.batch_requests(1234, 256):
+        u, v = workloads.interval(l, f21, n21)
+        reqs.append((f21, n21, math.isqrt(v)))
+    numbers = sum(n << (l + 1) for (_, n, _) in reqs)
+    pr = api.Primes(max(B for (_, _, B) in reqs))
+    outs = []
+    for (f, n, B) in reqs:
+        S, c = api.alloc(l, n)
+        outs.append((f, n, B, S, c))
+    ctx = api.Context()
+    t = time.perf_counter()
+    tune = autotune.tune_batch(pr, l, outs, ctx=ctx, log=log)
+    tune_s = time.perf_counter() - t
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / k
+
+    ms_batch = timed(lambda: ctx.batch(pr, l, outs, tune=tune), steps)
+    bit_exact = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch_1234.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        bit_exact = True
+        for (f, n, B, S, c), r in zip(outs, g["requests"]):
+            ch = c.cpu().numpy().view(np.uint32)
+            if hashlib.sha256(ch.astype("<u4").tobytes()).hexdigest() != r["counts_sha256"] or \
+                    hashlib.sha256(S.cpu().numpy().tobytes()).hexdigest() != r["S_sha256"]:
+                bit_exact = False
+                break
+
+    def plain_loop():
+        for (f, n, B, S, c) in outs:
+            ctx.sieve(l, f, n, B, S, c, primes=pr)
+
+    def init_loop():
+        for (f, n, B, S, c) in outs:
+            api.sieve_init(l, f, n, B, S, c)
+
+    ms_loop = timed(plain_loop, 2)
+    ms_init = timed(init_loop, 1)
+    ctx.check_device_errors()
+    return {"workload": "256 requests, seed 1234: centres log-uniform in [1e6, 1e15], widths log-uniform in "
+                        "[2^20, 2^30] numbers in whole 2^21-number blocks, B = isqrt(v) each (l=20)",
+            "numbers": numbers, "tune": tune, "autotune_s": round(tune_s, 2),
+            "batched": {"ms": ms_batch, "numbers_per_s": numbers / (ms_batch * 1e-3)},
+            "plain_loop_shared_table": {"ms": ms_loop, "numbers_per_s": numbers / (ms_loop * 1e-3)},
+            "plain_loop_sieve_init": {"ms": ms_init, "numbers_per_s": numbers / (ms_init * 1e-3)},
+            "speedup_vs_plain_loop": ms_loop / ms_batch, "bit_exact": bit_exact}
+
+
+def run_serving_bench(seconds, tune):
+    """Open-loop replay of the seeded Poisson stream (seed 99, 200 requests/s,
+    90% as in the batch workload, 10% of width 2^28 centred in [1e16, 2^62]) for the
+    first `seconds` seconds, 64 GB budget: continuous batching against a first come
+    first served plain-kernel server."""
+    from paper_1111_3297_amd import api, serve
+    l = 20
+    reqs = serve.serving_requests(l=l, limit_s=seconds)
+    pr = api.Primes(max(r.B for r in reqs))
+    ex = serve.GpuExecutor(pr, l, slots=3, tune=tune)
+    _, st = serve.Server(ex, l=l, budget_bytes=64 << 30).run(reqs)
+    _, st0 = serve.Server(serve.PlainExecutor(pr, l), l=l, budget_bytes=64 << 30, max_group=1).run(reqs)
+    keep = ("requests", "numbers", "span_s", "numbers_per_s", "p50_ms", "p99_ms", "max_ms", "peak_bytes")
+    return {"workload": "Poisson stream seed 99, 200 req/s, first %g s of 60 s, B = isqrt(v), 64 GB budget" % seconds,
+            "continuous_batching": {k: st[k] for k in keep},
+            "plain_fcfs": {k: st0[k] for k in keep}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +237,8 @@ def main():
     ap.add_argument("--workload", default="interval_1e12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--also", default="interval_2p60", help="comma list of extra plain workloads to report")
+    ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches (0: skip the batch bench)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of the request stream to replay (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -196,6 +283,13 @@ def main():
                  | {"kernels_ms_per_step": {kk: round(x["total_ms"], 4) for kk, x in r["kernels"].items()}}
                  for k, r in also.items()},
     }
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    tune = None
+    if args.batch_steps > 0:
+        out["batch"] = run_batch_bench(args.batch_steps, log)
+        tune = out["batch"]["tune"]
+    if args.serve_seconds > 0:
+        out["serving"] = run_serving_bench(args.serve_seconds, tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"])
     print(json.dumps(out), flush=True)

@@ -1,0 +1,115 @@
+"""CPU tests of the serving scheduler (paper_1111_3297_amd/serve.py) with a fake
+executor backed by the CPU oracle and a virtual clock: admission never exceeds
+the byte budget, requests start first come first served, every request gets the
+oracle's counts, and latency is measured from the scheduled arrival."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1111_3297_amd import serve
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class FakeExecutor:
+    """Completes a group `service_s` seconds of virtual time after submission."""
+
+    def __init__(self, clock, l, slots=2, service_s=0.01, scratch=1000):
+        self.clock, self.l, self.nslots, self.service_s, self.scratch = clock, l, slots, service_s, scratch
+        self.busy = 0
+        self.order = []
+
+    def free_slots(self):
+        return self.nslots - self.busy
+
+    def scratch_bytes(self, reqs):
+        return self.scratch * len(reqs)
+
+    def submit(self, reqs):
+        self.busy += 1
+        self.order.extend(r.rid for r in reqs)
+        return {"reqs": reqs, "t_done": self.clock.now() + self.service_s}
+
+    def done(self, h):
+        return self.clock.now() >= h["t_done"]
+
+    def finish(self, h):
+        self.busy -= 1
+        out = {}
+        for r in h["reqs"]:
+            _, c = O.sieve(self.l, r.f, r.n, r.B)
+            out[r.rid] = {"counts": c}
+        return out
+
+
+def make_requests(l, k, rate, seed=3):
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for rid in range(k):
+        t += rng.exponential(1.0 / rate)
+        n = int(rng.integers(1, 4))
+        f = int(rng.integers(0, 1 << 20))
+        u, v = O.interval(l, f, n)
+        out.append(serve.Request(rid, t, f, n, math.isqrt(v)))
+    return out
+
+
+def test_all_requests_served_with_oracle_counts_in_arrival_order():
+    clock = FakeClock()
+    l = 10
+    ex = FakeExecutor(clock, l, slots=2, service_s=0.005)
+    srv = serve.Server(ex, l=l, budget_bytes=1 << 30, clock=clock.now, sleep=clock.sleep)
+    reqs = make_requests(l, 60, rate=500.0)
+    res, st = srv.run(reqs)
+    assert sorted(res) == [r.rid for r in reqs]
+    assert ex.order == [r.rid for r in reqs]          # first come first served
+    for r in reqs:
+        _, c = O.sieve(l, r.f, r.n, r.B)
+        assert np.array_equal(res[r.rid]["counts"], c)
+    assert st["p50_ms"] >= 5.0 - 1e-6                  # at least the service time
+    assert st["p99_ms"] >= st["p50_ms"]
+
+
+def test_budget_is_never_exceeded():
+    clock = FakeClock()
+    l = 10
+    ex = FakeExecutor(clock, l, slots=8, service_s=0.05, scratch=4000)
+    per = serve.request_bytes(l, 3) + 4000
+    budget = 5 * per
+    srv = serve.Server(ex, l=l, budget_bytes=budget, clock=clock.now, sleep=clock.sleep)
+    reqs = make_requests(l, 40, rate=2000.0, seed=5)
+    res, st = srv.run(reqs)
+    assert len(res) == 40
+    assert st["peak_bytes"] <= budget
+
+
+def test_request_larger_than_budget_is_rejected():
+    clock = FakeClock()
+    l = 10
+    ex = FakeExecutor(clock, l)
+    srv = serve.Server(ex, l=l, budget_bytes=10, clock=clock.now, sleep=clock.sleep)
+    with pytest.raises(ValueError):
+        srv.run(make_requests(l, 2, rate=10.0))
+
+
+def test_latency_counts_from_scheduled_arrival_when_slots_are_full():
+    clock = FakeClock()
+    l = 10
+    ex = FakeExecutor(clock, l, slots=1, service_s=0.1)
+    srv = serve.Server(ex, l=l, budget_bytes=1 << 30, max_group=1, clock=clock.now, sleep=clock.sleep)
+    reqs = [serve.Request(k, 0.0, 5 + k, 1, 100) for k in range(3)]
+    res, st = srv.run(reqs)
+    # one slot, one request per group: completions at 0.1, 0.2, 0.3 s after arrival 0
+    assert abs(st["max_ms"] - 300.0) < 1.0
+    assert abs(st["p50_ms"] - 200.0) < 1.0
