@@ -239,7 +239,23 @@ def main():
     ap.add_argument("--also", default="interval_2p60", help="comma list of extra plain workloads to report")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches (0: skip the batch bench)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of the request stream to replay (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run the library's plain copy kernel over this many bytes, 5 times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        from paper_1111_3297_amd import _lib
+        import ctypes
+        nb = args.copy_calibration - args.copy_calibration % 16
+        a = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            _lib.check(_lib.load().sieve_copy_calibration(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                                          nb, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                       "sieve_copy_calibration")
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the design of a sharded run is described in DESIGN.md); use --gpus 1", file=sys.stderr)

@@ -69,11 +69,13 @@ typedef enum {
  *               of Section 3.2.2.  9 <= wave_log2 <= wheel_log2 <= medium_log2.
  *               Defaults 9 and min(tile_log2-7, medium_log2) (at least 9).
  *   bins_log2   log2 of the number of large-prime buckets per chunk, 8..15.
- *   groups      workgroups of the bucket-fill kernels, 64..2048 (rounded down to
- *               a multiple of ranges).
- *   ranges      the buckets of a chunk are split into this many ranges (1, 2, 4
- *               or 8; default 8) and workgroup g fills range g mod ranges, so the
- *               workgroups of one XCD append to one range only.
+ *   groups      workgroups of the bucket-fill kernels per chunk, 64..2048
+ *               (rounded down to a multiple of ranges); default 1024.  Each takes
+ *               a contiguous slice of the large primes of equal estimated work.
+ *   ranges      the buckets of a chunk are split into this many ranges of bins
+ *               (default 1), each filled by groups/ranges workgroups over all large
+ *               primes: fewer bins per workgroup allow larger LDS stages, at the
+ *               cost of visiting every large prime once per range.
  *   bin_log2    log2 of one bucket's width in bits, min(tile_log2,16)..tile_log2.
  *               Up to 16 a hit is stored as a 16-bit in-bucket offset, above 16
  *               as a 32-bit one.
@@ -179,14 +181,17 @@ int sieve_copy_calibration(const void *src_dev, void *dst_dev, uint64_t nbytes, 
 /* --- inspection (tests) ---
  * Runs the offset and bucket-fill kernels for the first chunk of (l, f, n, B) and
  * copies the bucket layout to host memory: bin_start (nbins+1 entries) and the
- * in-bin offsets of every large-prime hit, widened to 32 bits (entries, up to cap).  Returns
- * the number of bins in *nbins, the bin width log2 in *bin_log2, the number of
- * bits covered in *chunk_bits and the number of large primes in *nlarge.
- * Synchronises. */
+ * in-bin offsets of every large-prime hit, widened to 32 bits (entries, up to cap).  A
+ * bin's entries are its hits, each at least once, plus padding that repeats hits of
+ * the bin: at most *pad_per_bin extra entries per bin (each workgroup's region of a
+ * bin is rounded up to 16 bytes).  Returns the number of bins in *nbins, the bin width log2 in
+ * *bin_log2, the number of bits covered in *chunk_bits and the number of large
+ * primes in *nlarge.  Synchronises. */
 int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune *tune,
                         uint32_t *bin_start_host, uint32_t bin_cap, uint32_t *entries_host,
                         uint64_t entry_cap, uint32_t *nbins, uint32_t *bin_log2,
-                        uint64_t *chunk_bits, uint64_t *nlarge, uint64_t *nentries);
+                        uint64_t *chunk_bits, uint64_t *nlarge, uint64_t *nentries,
+                        uint32_t *pad_per_bin);
 
 #ifdef __cplusplus
 }

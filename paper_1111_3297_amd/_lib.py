@@ -27,7 +27,10 @@ class SieveError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
         name = STATUS.get(status, str(status))
-        super().__init__("%s failed: %s (%s)" % (what, name, strerror(status) if _lib else ""))
+        extra = ""
+        if _lib is not None and status == -5:
+            extra = ", hipError %d" % _lib.sieve_last_hip_error()
+        super().__init__("%s failed: %s (%s%s)" % (what, name, strerror(status) if _lib else "", extra))
 
 
 class Tune(ctypes.Structure):
@@ -79,7 +82,7 @@ def load():
         "sieve_copy_calibration": (i32, [vp, vp, u64, vp]),
         "sieve_debug_buckets": (i32, [u32, u64, u64, u64, ctypes.POINTER(Tune), vp, u32, vp, u64,
                                       ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64),
-                                      ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+                                      ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

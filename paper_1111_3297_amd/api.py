@@ -170,13 +170,15 @@ class Primes:
 def debug_buckets(l, f, n, B, tune=None, entry_cap=1 << 26):
     """First chunk's bucket layout (include/sieve.h: sieve_debug_buckets); synchronises."""
     import numpy as np
-    nbins, blog, cb, nl, ne = (ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64(),
-                               ctypes.c_uint64())
+    nbins, blog, cb, nl, ne, pad = (ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64(),
+                                    ctypes.c_uint64(), ctypes.c_uint32())
     bins = np.zeros(1 << 16, dtype=np.uint32)
     ent = np.zeros(entry_cap, dtype=np.uint32)
     L.check(L.load().sieve_debug_buckets(l, f, n, B, _tune(tune), bins.ctypes.data_as(ctypes.c_void_p), bins.size,
                                          ent.ctypes.data_as(ctypes.c_void_p), entry_cap, ctypes.byref(nbins),
-                                         ctypes.byref(blog), ctypes.byref(cb), ctypes.byref(nl), ctypes.byref(ne)),
+                                         ctypes.byref(blog), ctypes.byref(cb), ctypes.byref(nl), ctypes.byref(ne),
+                                         ctypes.byref(pad)),
             "sieve_debug_buckets")
     return {"bin_start": bins[:nbins.value + 1].copy(), "entries": ent[:min(ne.value, entry_cap)].copy(),
-            "bin_log2": blog.value, "chunk_bits": cb.value, "nlarge": nl.value, "nentries": ne.value}
+            "bin_log2": blog.value, "chunk_bits": cb.value, "nlarge": nl.value, "nentries": ne.value,
+            "pad_per_bin": pad.value}

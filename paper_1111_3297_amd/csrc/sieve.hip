@@ -35,7 +35,7 @@ thread_local int g_last_hip = 0;
 
 constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
 constexpr uint32_t kGenTile = 20;             // tile of the prime generator
-constexpr uint32_t kRanges = 8;               // bucket bin ranges (one per XCD)
+constexpr uint32_t kRanges = 1;               // minimum bucket ranges per chunk
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -107,7 +107,7 @@ int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
   if (r->binslog < 8 || r->binslog > 15) return SIEVE_E_ARG;
   r->R = t->ranges ? t->ranges : kRanges;
   if (r->R != 1 && r->R != 2 && r->R != 4 && r->R != 8) return SIEVE_E_ARG;
-  r->groups = t->groups ? t->groups : 256;
+  r->groups = t->groups ? t->groups : 1024;
   if (r->groups < 64 || r->groups > 2048) return SIEVE_E_ARG;
   r->groups -= r->groups % r->R;
   return SIEVE_OK;
@@ -146,12 +146,19 @@ struct sieve_ctx {
   hipEvent_t done = nullptr;
   // scratch
   DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk;
-  // batch scratch and the host copies of its tables (kept until the next call)
-  DevBuf b_req, b_blk, b_rd, b_blk2rd, b_seg0, b_tcnt, b_queue;
+  // batch scratch and the host copies of its tables
+  DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, thr;
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk;
-  std::vector<sv::RangeDesc> h_rd;
-  std::vector<uint32_t> h_blk2rd, h_seg0;
+  std::vector<uint32_t> h_seg0;
+  std::vector<sv::BucketJob> h_jobs;
+  std::vector<uint32_t> h_blk2job, h_thr;
+  // pinned staging for host-to-device table copies; reused only after the
+  // previous call's copies have completed (pin_ev)
+  void* pin = nullptr;
+  size_t pin_bytes = 0, pin_used = 0;
+  hipEvent_t pin_ev = nullptr;
+  bool pin_pending = false;
   DevBuf pat[32];
   uint32_t pat_words[32] = {0};
   sieve_primes own;  // table built by sieve_init / sieve_ctx_sieve
@@ -167,12 +174,15 @@ struct sieve_ctx {
 sieve_ctx::~sieve_ctx() {
   if (has_last) (void)hipStreamSynchronize(last_stream);
   DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk,
-                    &b_req, &b_blk, &b_rd, &b_blk2rd, &b_seg0, &b_tcnt, &b_queue, &own.P, &own.cnt};
+                    &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &thr, &own.P, &own.cnt};
   for (DevBuf* b : bufs) b->release();
   for (auto& b : pat) b.release();
   for (auto& e : ev_pool) (void)hipEventDestroy(e);
   for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   if (done) (void)hipEventDestroy(done);
+  if (pin_pending && pin_ev) (void)hipEventSynchronize(pin_ev);
+  if (pin) (void)hipHostFree(pin);
+  if (pin_ev) (void)hipEventDestroy(pin_ev);
 }
 
 namespace {
@@ -221,15 +231,119 @@ int collect_times(sieve_ctx* c) {
   return SIEVE_OK;
 }
 
+// Pinned staging: pin_begin waits for the previous call's copies, reserves
+// `total` bytes; upload copies a host table into it and enqueues the copy;
+// pin_end records the event that guards the next reuse.
+int pin_begin(sieve_ctx* c, size_t total) {
+  if (c->pin_pending) {
+    HIPCHK(hipEventSynchronize(c->pin_ev));
+    c->pin_pending = false;
+  }
+  c->pin_used = 0;
+  if (total > c->pin_bytes) {
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_bytes = 0;
+    const size_t want = std::max<size_t>(total * 2, 1 << 16);
+    HIPCHK(hipHostMalloc(&c->pin, want, hipHostMallocDefault));
+    c->pin_bytes = want;
+  }
+  if (!c->pin_ev) HIPCHK(hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming));
+  return SIEVE_OK;
+}
+int upload(sieve_ctx* c, hipStream_t s, void* dst, const void* src, size_t n) {
+  if (!n) return SIEVE_OK;
+  if (c->pin_used + n > c->pin_bytes) return SIEVE_E_ARG;
+  char* p = static_cast<char*>(c->pin) + c->pin_used;
+  memcpy(p, src, n);
+  HIPCHK(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, s));
+  c->pin_used += (n + 255) & ~size_t(255);
+  return SIEVE_OK;
+}
+int pin_end(sieve_ctx* c, hipStream_t s) {
+  if (c->pin_used) {
+    HIPCHK(hipEventRecord(c->pin_ev, s));
+    c->pin_pending = true;
+  }
+  return SIEVE_OK;
+}
+size_t pad256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Thresholds that split the large primes lo_p <= p <= B of a job into GR slices of
+// equal estimated work: span/p hits per prime in the job's span of bits plus a
+// per-prime cost of four hits (prime density 1/ln x; Mertens for the hit sum).
+void work_thresholds(double lo_p, double B, double span, uint32_t GR, uint32_t* thr) {
+  thr[0] = 0;
+  if (GR <= 1) return;
+  const int NS = 512;
+  std::vector<double> xs(NS + 1), W(NS + 1, 0.0);
+  const double r = std::log(std::max(B, lo_p + 1.0) / lo_p);
+  for (int i = 0; i <= NS; ++i) xs[i] = lo_p * std::exp(r * i / NS);
+  for (int i = 1; i <= NS; ++i) {
+    const double a = xs[i - 1], b = xs[i], mid = 0.5 * (a + b);
+    const double count = (b - a) / std::log(mid);
+    const double hits = span * (std::log(std::log(b)) - std::log(std::log(a)));
+    W[i] = W[i - 1] + hits + 2.0 * count;
+  }
+  int i = 1;
+  for (uint32_t q = 1; q < GR; ++q) {
+    const double target = W[NS] * q / GR;
+    while (i < NS && W[i] < target) ++i;
+    const double f = (W[i] > W[i - 1]) ? (target - W[i - 1]) / (W[i] - W[i - 1]) : 0.0;
+    const double x = xs[i - 1] + f * (xs[i] - xs[i - 1]);
+    thr[q] = (uint32_t)std::min(std::max(x, (double)thr[q - 1]), 4294967295.0);
+  }
+}
+
+// Dynamic LDS of one scatter launch whose jobs have at most max_rbins bins: stages of
+// kMinStageBytes per bin at least and up to kMaxStageBytes, plus the counters.  The
+// scatter is latency bound, so when the smallest stages fit in kScatterLdsPair the
+// launch stays within it and two workgroups (32 waves) share a CU.
+constexpr uint32_t kScatterLds = 152 * 1024;       // 2048 bins * (64 + 12) bytes
+constexpr uint32_t kScatterLdsPair = 72 * 1024;    // (160 KB - 2 * 8 KB static) / 2
+uint32_t scatter_lds(uint32_t max_rbins) {
+  const uint64_t per = sv::kStageWords * 4;
+  const uint64_t lo = (uint64_t)max_rbins * (per + sv::kMinStageBytes);
+  const uint64_t lim = lo <= kScatterLdsPair ? kScatterLdsPair : kScatterLds;
+  const uint64_t hi = std::min<uint64_t>((uint64_t)max_rbins * (per + sv::kMaxStageBytes), lim);
+  return (uint32_t)std::max(lo, hi);
+}
+
+// log2 of the stage entries per bin of a job with rbins bins in a launch of lds bytes
+// (the largest power of two that fits, at most 2^cap, at least kMinStageBytes).
+uint32_t stage_log2(uint32_t lds, uint32_t rbins, uint32_t esz, uint32_t cap = 31) {
+  const uint32_t per = std::min<uint32_t>(lds / rbins - sv::kStageWords * 4, sv::kMaxStageBytes) / esz;
+  uint32_t l2 = 0;
+  while ((2u << l2) <= per) ++l2;
+  uint32_t lo = 0;
+  while ((1u << lo) * esz < sv::kMinStageBytes) ++lo;
+  return std::max(lo, std::min(l2, cap));
+}
+
+// Sets the stage size of jobs [j0, j1) for one scatter launch and returns the
+// padding the group-rounded regions can add to the bucket (entries).
+uint64_t set_stages(std::vector<sv::BucketJob>& jobs, size_t j0, size_t j1, uint32_t esz, uint32_t* lds_out) {
+  uint32_t max_rbins = 1;
+  for (size_t k = j0; k < j1; ++k) max_rbins = std::max(max_rbins, jobs[k].rbins);
+  const uint32_t lds = scatter_lds(max_rbins);
+  uint64_t pad = 0;
+  for (size_t k = j0; k < j1; ++k) {
+    jobs[k].sbl = stage_log2(lds, jobs[k].rbins, esz, jobs[k].sbl);
+    pad += (uint64_t)jobs[k].GR * jobs[k].rbins * (16 / esz - 1);
+  }
+  if (lds_out) *lds_out = lds;
+  return pad;
+}
+
 int set_lds_limits() {
   static std::once_flag once;
   static int rc = SIEVE_OK;
   std::call_once(once, [] {
-    const int lim = 160 * 1024;
-    const void* fns[] = {(const void*)sv::k_bucket_count, (const void*)sv::k_bucket_scatter<uint16_t>,
-                         (const void*)sv::k_bucket_scatter<uint32_t>, (const void*)sv::k_bucket_count_batch,
-                         (const void*)sv::k_bucket_scatter_batch<uint16_t>,
-                         (const void*)sv::k_bucket_scatter_batch<uint32_t>};
+    // 160 KB per CU minus the bucket kernels' static LDS (kLoad primes and offsets,
+    // 8 KB); the scatter's stages and counters use at most 152 KB
+    const int lim = kScatterLds;
+    const void* fns[] = {(const void*)sv::k_bucket_count2, (const void*)sv::k_bucket_scatter2<uint16_t>,
+                         (const void*)sv::k_bucket_scatter2<uint32_t>};
     for (const void* f : fns)
       if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) rc = SIEVE_E_HIP;
   });
@@ -346,26 +460,77 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
   return SIEVE_OK;
 }
 
-// One bucket fill (counting sort of a chunk's large-prime hits by bin).
-int bucket_fill(sieve_ctx* c, const sv::BucketArgs& ba, uint32_t G, uint32_t esz, uint32_t cap, hipStream_t s) {
-  const uint32_t nbins = ba.nbins, rbins = ba.rbins;
-  const size_t hl = (size_t)rbins * 4;
+// Jobs of one chunk: ranges of at most sv::kMaxStageBins bins (at least
+// `ranges`), each served by GR = groups / R workgroups with equal-work slices.
+void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uint32_t groups, double lo_p, double B,
+                const uint32_t* Ptab, const sv::Plan* plan, const uint32_t* OFF_in, uint32_t* OFF_out,
+                uint32_t gbin_base, std::vector<sv::BucketJob>* jobs, std::vector<uint32_t>* blk2job,
+                std::vector<uint32_t>* thr, uint64_t* hg) {
+  uint32_t R = std::max<uint32_t>(ranges, (nbins + sv::kMaxStageBins - 1) / sv::kMaxStageBins);
+  R = std::min(R, nbins);
+  const uint32_t rbins = (nbins + R - 1) / R;
+  const uint32_t GR = std::max<uint32_t>(1, groups / R);
+  const uint32_t t0 = (uint32_t)thr->size();
+  thr->resize(t0 + GR);
+  work_thresholds(lo_p, B, (double)rbins * (double)(1ull << b), GR, thr->data() + t0);
+  // largest useful stage: about half a region's expected hits (larger stages would
+  // not fill before the last flush)
+  const uint32_t esz = b <= 16 ? 2 : 4;
+  const double exp_region = recip_sum_upper(lo_p, B) * std::ldexp(1.0, (int)b) / GR;
+  uint32_t sbl_cap = 0;
+  while ((2u << sbl_cap) * esz <= sv::kMaxStageBytes && (double)(2u << sbl_cap) <= exp_region / 2) ++sbl_cap;
+  for (uint32_t x = 0; x < R; ++x) {
+    sv::BucketJob J;
+    memset(&J, 0, sizeof J);
+    J.kb0 = x * rbins;
+    if (J.kb0 >= nbins) break;
+    J.Ptab = Ptab; J.plan = plan; J.OFF_in = OFF_in; J.OFF_out = OFF_out;
+    J.thr = reinterpret_cast<const uint32_t*>((uintptr_t)t0);   // index into thr, rebased after upload
+    J.cbits = cbits; J.b = b; J.rbins = std::min(rbins, nbins - J.kb0); J.update = (x + 1 == R) || (J.kb0 + rbins >= nbins);
+    J.GR = GR; J.block0 = (uint32_t)blk2job->size(); J.hg = (uint32_t)*hg; J.gbin0 = gbin_base + J.kb0;
+    J.sbl = sbl_cap;   // an upper bound here; set_stages fits it to the launch's LDS
+    *hg += (uint64_t)GR * J.rbins;
+    for (uint32_t q = 0; q < GR; ++q) blk2job->push_back((uint32_t)jobs->size());
+    jobs->push_back(J);
+    if (J.update) break;
+  }
+}
+
+// Counting sort of the hits of a set of jobs into the bucket array:
+// per-workgroup counts, scan over (bin, workgroup), staged scatter.
+int bucket_fill_jobs(sieve_ctx* c, const sv::BucketJob* djobs, const uint32_t* dblk2job, uint32_t njobs, uint32_t nblocks,
+                     uint32_t gbins, uint32_t max_rbins, uint32_t lds, uint32_t esz, uint32_t cap, hipStream_t s) {
   uint32_t* HG = c->HG.as<uint32_t>();
-  uint32_t* bstart = c->bstart.as<uint32_t>();
-  uint32_t* tot = bstart + nbins + 1;
-  const uint32_t gb = (nbins + 255) / 256;
-  STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count<<<G, 1024, hl, s>>>(ba, HG); }));
-  STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_total<<<gb, 256, 0, s>>>(HG, G, ba.R, rbins, nbins, tot); }));
-  STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, nbins, bstart); }));
-  STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_colprefix<<<gb, 256, 0, s>>>(HG, G, ba.R, rbins, nbins, bstart); }));
+  uint32_t* bst = c->bstart.as<uint32_t>();
+  uint32_t* tot = bst + gbins + 1;
+  const uint32_t gb = (gbins + 255) / 256;
+  const size_t lc = (size_t)max_rbins * 4, ls = lds;
+  STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count2<<<nblocks, 1024, lc, s>>>(djobs, dblk2job, HG); }));
+  STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_jobs<<<gb, 256, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 0); }));
+  STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, gbins, bst); }));
+  STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_jobs<<<gb, 256, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 1); }));
   if (esz == 2)
     STCHK(launch(c, "k_bucket_scatter", s, [&] {
-      sv::k_bucket_scatter<uint16_t><<<G, 1024, hl, s>>>(ba, HG, c->bucket.as<uint16_t>(), cap, c->err.as<uint32_t>());
+      sv::k_bucket_scatter2<uint16_t><<<nblocks, 1024, ls, s>>>(djobs, dblk2job, HG, bst, c->bucket.as<uint16_t>(),
+                                                                 cap, c->err.as<uint32_t>());
     }));
   else
     STCHK(launch(c, "k_bucket_scatter", s, [&] {
-      sv::k_bucket_scatter<uint32_t><<<G, 1024, hl, s>>>(ba, HG, c->bucket.as<uint32_t>(), cap, c->err.as<uint32_t>());
+      sv::k_bucket_scatter2<uint32_t><<<nblocks, 1024, ls, s>>>(djobs, dblk2job, HG, bst, c->bucket.as<uint32_t>(),
+                                                                 cap, c->err.as<uint32_t>());
     }));
+  return SIEVE_OK;
+}
+
+// Uploads jobs / block map / thresholds (rebasing the jobs' threshold pointers).
+int upload_jobs(sieve_ctx* c, hipStream_t s) {
+  STCHK(c->jobs.ensure(c->h_jobs.size() * sizeof(sv::BucketJob) + 64));
+  STCHK(c->blk2job.ensure(c->h_blk2job.size() * 4 + 64));
+  STCHK(c->thr.ensure(c->h_thr.size() * 4 + 64));
+  for (auto& J : c->h_jobs) J.thr = c->thr.as<uint32_t>() + reinterpret_cast<uintptr_t>(J.thr);
+  STCHK(upload(c, s, c->jobs.p, c->h_jobs.data(), c->h_jobs.size() * sizeof(sv::BucketJob)));
+  STCHK(upload(c, s, c->blk2job.p, c->h_blk2job.data(), c->h_blk2job.size() * 4));
+  STCHK(upload(c, s, c->thr.p, c->h_thr.data(), c->h_thr.size() * 4));
   return SIEVE_OK;
 }
 
@@ -390,16 +555,58 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   STCHK(get_pattern(c, B, s, &pat, &per, &patw, &pmask));
   const uint32_t b = R.b;
   const uint32_t esz = b <= 16 ? 2 : 4;                        // bytes per bucket entry
-  const uint32_t G = R.groups;
   const uint64_t chunk_max = std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits);  // bits per bucket fill
+  // every chunk of every launch, with its bucket jobs
+  struct Chunk { uint64_t ls, lbits, cs, cbits; uint32_t nbins, j0, j1, b0, b1, max_rbins, lds; };
+  std::vector<Chunk> chunks;
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_thr.clear();
+  uint64_t hg_max = 0, cap = 0, pad_max = 0;
+  uint32_t nbins_max = 0;
   if (large) {
-    STCHK(c->HG.ensure((size_t)G * (((1ull << R.binslog) + R.R - 1) / R.R) * 4));
-    STCHK(c->bstart.ensure(((2ull << R.binslog) + 2) * 4));   // bin_start, then bin totals
-    const uint64_t cb = std::min<uint64_t>(chunk_max, NB);
     const double rs = recip_sum_upper((double)med_lim, (double)B);
-    const uint64_t cap = (uint64_t)(1.02 * rs * (double)cb) + nL_ub + 4096;
+    cap = (uint64_t)(1.02 * rs * (double)std::min<uint64_t>(chunk_max, NB)) + nL_ub + 4096;
     if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
+  }
+  for (uint64_t ls = 0; ls < NB; ls += kLaunchBits) {
+    const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB - ls);
+    uint32_t off_cur = 0;   // which half of OFF holds the offsets of the current chunk
+    for (uint64_t cs = 0; cs < lbits; cs += chunk_max) {
+      Chunk ch;
+      ch.ls = ls; ch.lbits = lbits; ch.cs = cs; ch.cbits = std::min<uint64_t>(chunk_max, lbits - cs);
+      ch.nbins = (uint32_t)((ch.cbits + (1ull << b) - 1) >> b);
+      ch.j0 = (uint32_t)c->h_jobs.size(); ch.b0 = (uint32_t)c->h_blk2job.size();
+      ch.max_rbins = 1;
+      if (large) {
+        uint64_t hg = 0;
+        const uint32_t* oin = c->OFF.as<uint32_t>() + (size_t)off_cur * nL_ub;
+        uint32_t* oout = c->OFF.as<uint32_t>() + (size_t)(1 - off_cur) * nL_ub;
+        const size_t jb = c->h_jobs.size();
+        chunk_jobs(ch.nbins, (uint32_t)ch.cbits, b, R.R, R.groups, (double)med_lim, (double)B, pr->P.as<uint32_t>(),
+                   plan, oin, oout, 0, &c->h_jobs, &c->h_blk2job, &c->h_thr, &hg);
+        for (size_t k = jb; k < c->h_jobs.size(); ++k) {   // block numbers and job indices relative to the chunk
+          c->h_jobs[k].block0 -= ch.b0;
+          ch.max_rbins = std::max(ch.max_rbins, c->h_jobs[k].rbins);
+        }
+        pad_max = std::max(pad_max, set_stages(c->h_jobs, jb, c->h_jobs.size(), esz, &ch.lds));
+        for (size_t k = ch.b0; k < c->h_blk2job.size(); ++k) c->h_blk2job[k] -= ch.j0;
+        hg_max = std::max(hg_max, hg);
+        nbins_max = std::max(nbins_max, ch.nbins);
+        off_cur ^= 1u;
+      }
+      ch.j1 = (uint32_t)c->h_jobs.size(); ch.b1 = (uint32_t)c->h_blk2job.size();
+      chunks.push_back(ch);
+    }
+  }
+  if (large) {
+    cap += pad_max;
+    if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
+    STCHK(c->HG.ensure(hg_max * 4 + 64));
+    STCHK(c->bstart.ensure(((size_t)2 * nbins_max + 2) * 4));   // bin_start, then bin totals
     STCHK(c->bucket.ensure(cap * esz));
+    STCHK(pin_begin(c, pad256(c->h_jobs.size() * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
+                           pad256(c->h_thr.size() * 4)));
+    STCHK(upload_jobs(c, s));
+    STCHK(pin_end(c, s));
   }
   STCHK(ensure_err(c, s));
   const bool count_atomic = L < l;
@@ -408,46 +615,37 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(counts, n, 0); }));
   }
   const uint32_t patG_step = (uint32_t)((1ull << L) % per);
-  for (uint64_t ls = 0; ls < NB; ls += kLaunchBits) {
-    const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB - ls);
-    const uint64_t G0 = F + ls;
-    const uint64_t off_ub = tab_ub;  // grid over primes >= 17
-    STCHK(launch(c, "k_offsets", s, [&] {
-      sv::k_offsets<<<(uint32_t)((off_ub + 255) / 256), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, lbits,
-                                                                     c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr);
-    }));
-    uint32_t off_cur = 0;  // which half of OFF holds the offsets of the current chunk
-    const uint64_t psq = isqrt_u64(2 * G0 + 1);
-    for (uint64_t cs = 0; cs < lbits; cs += chunk_max) {
-      const uint64_t cbits = std::min<uint64_t>(chunk_max, lbits - cs);
-      const uint32_t ntiles = (uint32_t)((cbits + (1ull << L) - 1) >> L);
-      const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
-      const double rs = large ? recip_sum_upper((double)med_lim, (double)B) : 0;
-      const uint64_t cap = (uint64_t)(1.02 * rs * (double)std::min<uint64_t>(chunk_max, NB)) + nL_ub + 4096;
-      if (large) {
-        sv::BucketArgs ba;
-        ba.P = pr->P.as<uint32_t>(); ba.plan = plan;
-        ba.OFF_in = c->OFF.as<uint32_t>() + (size_t)off_cur * nL_ub;
-        ba.OFF_out = c->OFF.as<uint32_t>() + (size_t)(1 - off_cur) * nL_ub;
-        ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins;
-        ba.R = R.R; ba.rbins = (nbins + R.R - 1) / R.R;
-        STCHK(bucket_fill(c, ba, G, esz, (uint32_t)cap, s));
-        off_cur ^= 1u;
-      }
-      sv::TileArgs ta;
-      memset(&ta, 0, sizeof ta);
-      ta.G0 = G0; ta.lbits = (uint32_t)lbits; ta.t0 = (uint32_t)(cs >> L); ta.L = L; ta.l = l;
-      ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
-      ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
-      ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
-      ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
-      ta.b = b; ta.nbins = nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
-      ta.S = S + (ls >> 5); ta.counts = counts + (ls >> l); ta.count_atomic = count_atomic ? 1 : 0;
-      if (esz == 2)
-        STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(L, ntiles, s, ta); }));
-      else
-        STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(L, ntiles, s, ta); }));
+  const sv::BucketJob* djobs = c->jobs.as<sv::BucketJob>();
+  const uint32_t* dblk = c->blk2job.as<uint32_t>();
+  uint64_t cur_ls = ~0ull;
+  for (const Chunk& ch : chunks) {
+    const uint64_t G0 = F + ch.ls;
+    if (ch.ls != cur_ls) {
+      cur_ls = ch.ls;
+      const uint64_t off_ub = tab_ub;  // grid over primes >= 17
+      STCHK(launch(c, "k_offsets", s, [&] {
+        sv::k_offsets<<<(uint32_t)((off_ub + 255) / 256), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits,
+                                                                       c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr);
+      }));
     }
+    const uint64_t psq = isqrt_u64(2 * G0 + 1);
+    const uint32_t ntiles = (uint32_t)((ch.cbits + (1ull << L) - 1) >> L);
+    if (large)
+      STCHK(bucket_fill_jobs(c, djobs + ch.j0, dblk + ch.b0, ch.j1 - ch.j0, ch.b1 - ch.b0, ch.nbins, ch.max_rbins, ch.lds,
+                             esz, (uint32_t)cap, s));
+    sv::TileArgs ta;
+    memset(&ta, 0, sizeof ta);
+    ta.G0 = G0; ta.lbits = (uint32_t)ch.lbits; ta.t0 = (uint32_t)(ch.cs >> L); ta.L = L; ta.l = l;
+    ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
+    ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
+    ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
+    ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
+    ta.b = b; ta.nbins = ch.nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
+    ta.S = S + (ch.ls >> 5); ta.counts = counts + (ch.ls >> l); ta.count_atomic = count_atomic ? 1 : 0;
+    if (esz == 2)
+      STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(L, ntiles, s, ta); }));
+    else
+      STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(L, ntiles, s, ta); }));
   }
   return SIEVE_OK;
 }
@@ -669,7 +867,7 @@ int sieve_copy_calibration(const void* src_dev, void* dst_dev, uint64_t nbytes, 
 int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune* tune,
                         uint32_t* bin_start_host, uint32_t bin_cap, uint32_t* entries_host, uint64_t entry_cap,
                         uint32_t* nbins_out, uint32_t* bin_log2, uint64_t* chunk_bits, uint64_t* nlarge,
-                        uint64_t* nentries) {
+                        uint64_t* nentries, uint32_t* pad_per_bin) {
   uint64_t F, NB;
   STCHK(check_interval(l, f, n, B, &F, &NB));
   Resolved R;
@@ -696,19 +894,28 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   const uint32_t b = R.b, esz = b <= 16 ? 2 : 4;
   const uint64_t cbits = std::min<uint64_t>(std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits), lbits);
   const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
-  const uint32_t G = R.groups;
-  const uint32_t rbins = (nbins + R.R - 1) / R.R;
-  STCHK(c->HG.ensure((size_t)G * rbins * 4));
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_thr.clear();
+  uint64_t hg = 0;
+  chunk_jobs(nbins, (uint32_t)cbits, b, R.R, R.groups, (double)med_lim, (double)B, c->own.P.as<uint32_t>(), plan,
+             c->OFF.as<uint32_t>(), c->OFF.as<uint32_t>() + tab_ub, 0, &c->h_jobs, &c->h_blk2job, &c->h_thr, &hg);
+  uint32_t max_rbins = 1;
+  for (auto& J : c->h_jobs) max_rbins = std::max(max_rbins, J.rbins);
+  STCHK(c->HG.ensure(hg * 4 + 64));
   STCHK(c->bstart.ensure((2 * nbins + 2) * 4));
+  uint32_t lds = 0, pad_bin = 0;
+  const uint64_t pad = set_stages(c->h_jobs, 0, c->h_jobs.size(), esz, &lds);
+  for (auto& J : c->h_jobs) pad_bin = std::max(pad_bin, J.GR * (16 / esz - 1));
   const double rs = recip_sum_upper((double)med_lim, (double)B);
-  const uint64_t cap = (uint64_t)(1.02 * rs * (double)cbits) + tab_ub + 4096;
+  const uint64_t cap = (uint64_t)(1.02 * rs * (double)cbits) + tab_ub + 4096 + pad;
+  if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
   STCHK(c->bucket.ensure(cap * esz));
   STCHK(ensure_err(c, s));
-  sv::BucketArgs ba;
-  ba.P = c->own.P.as<uint32_t>(); ba.plan = plan;
-  ba.OFF_in = c->OFF.as<uint32_t>(); ba.OFF_out = c->OFF.as<uint32_t>() + tab_ub;
-  ba.cbits = (uint32_t)cbits; ba.b = b; ba.nbins = nbins; ba.R = R.R; ba.rbins = rbins;
-  STCHK(bucket_fill(c, ba, G, esz, (uint32_t)cap, s));
+  STCHK(pin_begin(c, pad256(c->h_jobs.size() * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
+                         pad256(c->h_thr.size() * 4)));
+  STCHK(upload_jobs(c, s));
+  STCHK(pin_end(c, s));
+  STCHK(bucket_fill_jobs(c, c->jobs.as<sv::BucketJob>(), c->blk2job.as<uint32_t>(), (uint32_t)c->h_jobs.size(),
+                         (uint32_t)c->h_blk2job.size(), nbins, max_rbins, lds, esz, (uint32_t)cap, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<uint32_t> bs(nbins + 1);
   HIPCHK(hipMemcpy(bs.data(), c->bstart.p, (nbins + 1) * 4, hipMemcpyDeviceToHost));
@@ -719,6 +926,7 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   if (chunk_bits) *chunk_bits = cbits;
   if (nlarge) *nlarge = hp.np - hp.iM;
   if (nentries) *nentries = bs[nbins];
+  if (pad_per_bin) *pad_per_bin = pad_bin;
   memcpy(bin_start_host, bs.data(), std::min<uint32_t>(bin_cap, nbins + 1) * 4);
   if (entries_host) {
     const uint64_t ne = std::min<uint64_t>(std::min<uint64_t>(entry_cap, bs[nbins]), cap);
@@ -819,10 +1027,11 @@ uint64_t batch_bytes(const std::vector<Window>& W, const Resolved& R, uint32_t l
     off += pi_upper(w.B) + 16;
     tiles += (w.lbits + (1u << R.L) - 1) >> R.L;
     if (w.B >= med_lim) {
-      cap += window_cap(w, med_lim);
       const uint64_t nb = (w.lbits + (1ull << R.b) - 1) >> R.b;
+      // at most 256 workgroups per request, each with a group-rounded region per bin
+      cap += window_cap(w, med_lim) + 256 * nb * (16 / esz - 1);
       bins += nb;
-      hg += nb * 32;  // at most 32 blocks per range
+      hg += nb * 256;
     }
   }
   (void)l;
@@ -851,8 +1060,6 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   // per-window layout
   c->h_req.assign(nw, sv::BatchReq());
   c->h_blk.clear();
-  c->h_rd.clear();
-  c->h_blk2rd.clear();
   c->h_seg0.assign(nw, 0);
   uint64_t qp_tot = 0, off_tot = 0, cap_tot = 0, hg_tot = 0;
   uint32_t items = 0, gbins = 0, tcnt = 0, seg_tot = 0, max_rbins = 1;
@@ -883,42 +1090,65 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     if (X.B >= med_lim) {
       q.nbins = (X.lbits + (1u << b) - 1) >> b;
       q.bin_base = gbins;
-      const uint32_t Rw = std::min<uint32_t>(R.R, q.nbins);
-      const uint32_t rbins = (q.nbins + Rw - 1) / Rw;
-      const uint32_t GR = (uint32_t)std::min<uint64_t>(32, std::max<uint64_t>(1, (q.off_cap + 16383) / 16384));
-      for (uint32_t x = 0; x < Rw; ++x) {
-        sv::RangeDesc d;
-        d.req = w; d.kb0 = x * rbins; d.kb1 = std::min(q.nbins, d.kb0 + rbins);
-        if (d.kb0 >= d.kb1) break;
-        d.rbins = rbins; d.block0 = (uint32_t)c->h_blk2rd.size(); d.GR = GR; d.hg = (uint32_t)hg_tot;
-        d.gbin0 = gbins + d.kb0;
-        hg_tot += (uint64_t)GR * rbins;
-        for (uint32_t k = 0; k < GR; ++k) c->h_blk2rd.push_back((uint32_t)c->h_rd.size());
-        c->h_rd.push_back(d);
-      }
-      max_rbins = std::max(max_rbins, rbins);
       gbins += q.nbins;
       cap_tot += window_cap(X, med_lim);
     }
   }
-  if (cap_tot >= 0xFFFFFFFFull || hg_tot >= 0xFFFFFFFFull || (size_t)max_rbins * 4 > 160 * 1024) return SIEVE_E_NOMEM;
+  // bucket jobs: workgroups shared out by estimated work (hits + primes)
+  std::vector<double> work(nw, 0.0);
+  double work_tot = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    const sv::BatchReq& q = c->h_req[w];
+    if (!q.nbins) continue;
+    const double hits = recip_sum_upper((double)med_lim, (double)q.B) * q.lbits;
+    work[w] = hits + 2.0 * (double)pi_upper(q.B);
+    work_tot += work[w];
+  }
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_thr.clear();
+  for (uint32_t w = 0; w < nw; ++w) {
+    const sv::BatchReq& q = c->h_req[w];
+    if (!q.nbins) continue;
+    const uint32_t groups = (uint32_t)std::min<double>(256.0, std::max<double>(1.0, std::round((double)R.groups * 2 * work[w] / work_tot)));
+    const size_t jb = c->h_jobs.size();
+    chunk_jobs(q.nbins, q.lbits, b, R.R, groups, (double)med_lim, (double)q.B, pr->P.as<uint32_t>(),
+               reinterpret_cast<const sv::Plan*>((uintptr_t)w), reinterpret_cast<const uint32_t*>((uintptr_t)w), nullptr,
+               q.bin_base, &c->h_jobs, &c->h_blk2job, &c->h_thr, &hg_tot);
+    for (size_t k = jb; k < c->h_jobs.size(); ++k) max_rbins = std::max(max_rbins, c->h_jobs[k].rbins);
+  }
+  if (max_rbins > sv::kMaxStageBins) return SIEVE_E_NOMEM;
+  uint32_t lds = 0;
+  cap_tot += set_stages(c->h_jobs, 0, c->h_jobs.size(), esz, &lds);
+  if (cap_tot >= 0xFFFFFFFFull || hg_tot >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
   // device buffers
   STCHK(c->Q0.ensure(qp_tot * 8 + 64));
   STCHK(c->OFF.ensure(off_tot * 4 + 64));
   STCHK(ensure_err(c, s));
-  for (sv::BatchReq& q : c->h_req) {
-    q.QP = c->Q0.as<uint2>() + reinterpret_cast<uintptr_t>(q.QP);
-    q.OFF = c->OFF.as<uint32_t>() + reinterpret_cast<uintptr_t>(q.OFF);
-  }
   STCHK(c->b_req.ensure(nw * sizeof(sv::BatchReq)));
   STCHK(c->b_blk.ensure(c->h_blk.size() * sizeof(uint2)));
   STCHK(c->b_seg0.ensure(nw * 4));
   STCHK(c->b_queue.ensure(64));
   if (seg_long) STCHK(c->b_tcnt.ensure((size_t)tcnt * 4 + 64));
-  HIPCHK(hipMemcpyAsync(c->b_req.p, c->h_req.data(), nw * sizeof(sv::BatchReq), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(c->b_blk.p, c->h_blk.data(), c->h_blk.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(c->b_seg0.p, c->h_seg0.data(), nw * 4, hipMemcpyHostToDevice, s));
   sv::BatchReq* dreq = c->b_req.as<sv::BatchReq>();
+  for (sv::BatchReq& q : c->h_req) {
+    q.QP = c->Q0.as<uint2>() + reinterpret_cast<uintptr_t>(q.QP);
+    q.OFF = c->OFF.as<uint32_t>() + reinterpret_cast<uintptr_t>(q.OFF);
+  }
+  for (sv::BucketJob& J : c->h_jobs) {   // one chunk per request: no next-chunk offsets
+    const uintptr_t w = reinterpret_cast<uintptr_t>(J.plan);
+    J.plan = &dreq[w].plan;
+    J.OFF_in = c->h_req[w].OFF;
+    J.OFF_out = nullptr;
+    J.update = 0;
+  }
+  const uint32_t njobs = (uint32_t)c->h_jobs.size();
+  STCHK(pin_begin(c, pad256(nw * sizeof(sv::BatchReq)) + pad256(c->h_blk.size() * sizeof(uint2)) + pad256(nw * 4) +
+                         pad256(njobs * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
+                         pad256(c->h_thr.size() * 4)));
+  STCHK(upload(c, s, c->b_req.p, c->h_req.data(), nw * sizeof(sv::BatchReq)));
+  STCHK(upload(c, s, c->b_blk.p, c->h_blk.data(), c->h_blk.size() * sizeof(uint2)));
+  STCHK(upload(c, s, c->b_seg0.p, c->h_seg0.data(), nw * 4));
+  if (njobs) STCHK(upload_jobs(c, s));
+  STCHK(pin_end(c, s));
   STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<1, 64, 0, s>>>(c->b_queue.as<uint32_t>(), 16, 0); }));
   STCHK(launch(c, "k_plan_batch", s, [&] {
     sv::k_plan_batch<<<(nw + 63) / 64, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), dreq, nw,
@@ -928,51 +1158,21 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   STCHK(launch(c, "k_offsets_batch", s, [&] {
     sv::k_offsets_batch<<<nblk, 256, 0, s>>>(pr->P.as<uint32_t>(), dreq, c->b_blk.as<uint2>());
   }));
-  const uint32_t nrd = (uint32_t)c->h_rd.size();
   uint32_t cap32 = 0;
-  if (nrd) {
-    const uint32_t nbb = (uint32_t)c->h_blk2rd.size();
-    STCHK(c->b_rd.ensure(nrd * sizeof(sv::RangeDesc)));
-    STCHK(c->b_blk2rd.ensure(nbb * 4));
+  if (njobs) {
     STCHK(c->HG.ensure(hg_tot * 4 + 64));
     STCHK(c->bstart.ensure(((size_t)2 * gbins + 2) * 4));
     STCHK(c->bucket.ensure(cap_tot * esz));
-    HIPCHK(hipMemcpyAsync(c->b_rd.p, c->h_rd.data(), nrd * sizeof(sv::RangeDesc), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->b_blk2rd.p, c->h_blk2rd.data(), nbb * 4, hipMemcpyHostToDevice, s));
-    const sv::RangeDesc* drd = c->b_rd.as<sv::RangeDesc>();
-    const uint32_t* dbr = c->b_blk2rd.as<uint32_t>();
-    uint32_t* HG = c->HG.as<uint32_t>();
-    uint32_t* bst = c->bstart.as<uint32_t>();
-    uint32_t* tot = bst + gbins + 1;
-    const size_t hl = (size_t)max_rbins * 4;
     cap32 = (uint32_t)cap_tot;
-    STCHK(launch(c, "k_bucket_count", s, [&] {
-      sv::k_bucket_count_batch<<<nbb, 1024, hl, s>>>(pr->P.as<uint32_t>(), dreq, drd, dbr, b, HG);
-    }));
-    STCHK(launch(c, "k_bin_total", s, [&] {
-      sv::k_bin_batch<<<(gbins + 255) / 256, 256, 0, s>>>(HG, drd, nrd, gbins, tot, bst, 0);
-    }));
-    STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, gbins, bst); }));
-    STCHK(launch(c, "k_bin_colprefix", s, [&] {
-      sv::k_bin_batch<<<(gbins + 255) / 256, 256, 0, s>>>(HG, drd, nrd, gbins, tot, bst, 1);
-    }));
-    if (esz == 2)
-      STCHK(launch(c, "k_bucket_scatter", s, [&] {
-        sv::k_bucket_scatter_batch<uint16_t><<<nbb, 1024, hl, s>>>(pr->P.as<uint32_t>(), dreq, drd, dbr, b, HG,
-                                                                  c->bucket.as<uint16_t>(), cap32, c->err.as<uint32_t>());
-      }));
-    else
-      STCHK(launch(c, "k_bucket_scatter", s, [&] {
-        sv::k_bucket_scatter_batch<uint32_t><<<nbb, 1024, hl, s>>>(pr->P.as<uint32_t>(), dreq, drd, dbr, b, HG,
-                                                                  c->bucket.as<uint32_t>(), cap32, c->err.as<uint32_t>());
-      }));
+    STCHK(bucket_fill_jobs(c, c->jobs.as<sv::BucketJob>(), c->blk2job.as<uint32_t>(), njobs,
+                           (uint32_t)c->h_blk2job.size(), gbins, max_rbins, lds, esz, cap32, s));
   }
   int ncu = 0;
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)ncu * tiles_per_cu(L), items);
   uint32_t* tc = seg_long ? c->b_tcnt.as<uint32_t>() : nullptr;
-  const void* bk = nrd ? c->bucket.p : nullptr;
-  const uint32_t* bsp = nrd ? c->bstart.as<uint32_t>() : nullptr;
+  const void* bk = njobs ? c->bucket.p : nullptr;
+  const uint32_t* bsp = njobs ? c->bstart.as<uint32_t>() : nullptr;
   if (esz == 2)
     STCHK(launch(c, "k_tile_batch", s, [&] {
       launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
