@@ -36,6 +36,7 @@ thread_local int g_last_hip = 0;
 constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
 constexpr uint32_t kGenTile = 20;             // tile of the prime generator
 constexpr uint32_t kRanges = 1;               // minimum bucket ranges per chunk
+constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -469,7 +470,11 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
   uint32_t R = std::max<uint32_t>(ranges, (nbins + sv::kMaxStageBins - 1) / sv::kMaxStageBins);
   R = std::min(R, nbins);
   const uint32_t rbins = (nbins + R - 1) / R;
-  const uint32_t GR = std::max<uint32_t>(1, groups / R);
+  // workgroups per range: as given, but no more than one per kHitsPerGroup expected
+  // hits (small jobs would otherwise pay a set-up and a flush per idle workgroup)
+  const double range_hits = recip_sum_upper(lo_p, B) * (double)rbins * std::ldexp(1.0, (int)b);
+  const uint32_t GR = (uint32_t)std::max<double>(1.0, std::min<double>(std::max<uint32_t>(1, groups / R),
+                                                                       std::ceil(range_hits / kHitsPerGroup)));
   const uint32_t t0 = (uint32_t)thr->size();
   thr->resize(t0 + GR);
   work_thresholds(lo_p, B, (double)rbins * (double)(1ull << b), GR, thr->data() + t0);
@@ -503,12 +508,12 @@ int bucket_fill_jobs(sieve_ctx* c, const sv::BucketJob* djobs, const uint32_t* d
   uint32_t* HG = c->HG.as<uint32_t>();
   uint32_t* bst = c->bstart.as<uint32_t>();
   uint32_t* tot = bst + gbins + 1;
-  const uint32_t gb = (gbins + 255) / 256;
+  const uint32_t gb = (gbins + sv::kBinsPerBlock - 1) / sv::kBinsPerBlock;
   const size_t lc = (size_t)max_rbins * 4, ls = lds;
   STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count2<<<nblocks, 1024, lc, s>>>(djobs, dblk2job, HG); }));
-  STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_jobs<<<gb, 256, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 0); }));
+  STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_jobs<<<gb, 1024, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 0); }));
   STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, gbins, bst); }));
-  STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_jobs<<<gb, 256, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 1); }));
+  STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_jobs<<<gb, 1024, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 1); }));
   if (esz == 2)
     STCHK(launch(c, "k_bucket_scatter", s, [&] {
       sv::k_bucket_scatter2<uint16_t><<<nblocks, 1024, ls, s>>>(djobs, dblk2job, HG, bst, c->bucket.as<uint16_t>(),
