@@ -162,8 +162,6 @@ struct sieve_ctx {
   bool pin_pending = false;
   DevBuf pat[32];
   uint32_t pat_words[32] = {0};
-  DevBuf xpat;             // extended patterns of 17..61 (built once)
-  bool xpat_ready = false;
   sieve_primes own;  // table built by sieve_init / sieve_ctx_sieve
   // timing
   bool timing = false;
@@ -376,19 +374,6 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
   return SIEVE_OK;
 }
 
-// The extended patterns of the primes 17..61 (built on the device once per context).
-int get_xpattern(sieve_ctx* c, hipStream_t s, const uint32_t** xpat) {
-  if (!c->xpat_ready) {
-    STCHK(c->xpat.ensure((size_t)sv::kXPatWords * 4));
-    STCHK(launch(c, "k_xpattern", s, [&] {
-      sv::k_xpattern<<<(sv::kXPatWords + 255) / 256, 256, 0, s>>>(c->xpat.as<uint32_t>());
-    }));
-    c->xpat_ready = true;
-  }
-  *xpat = c->xpat.as<uint32_t>();
-  return SIEVE_OK;
-}
-
 // Launches the tile kernel instantiated for tile size 2^L and entry type E.
 template <typename E>
 void launch_tile(uint32_t L, uint32_t ntiles, hipStream_t s, const sv::TileArgs& ta) {
@@ -573,8 +558,6 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   if (large) STCHK(c->OFF.ensure(2 * nL_ub * 4 + 64));           // in / out halves
   const uint32_t* pat; uint32_t per, patw, pmask;
   STCHK(get_pattern(c, B, s, &pat, &per, &patw, &pmask));
-  const uint32_t* xpat;
-  STCHK(get_xpattern(c, s, &xpat));
   const uint32_t b = R.b;
   const uint32_t esz = b <= 16 ? 2 : 4;                        // bytes per bucket entry
   const uint64_t chunk_max = std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits);  // bits per bucket fill
@@ -660,7 +643,6 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     ta.G0 = G0; ta.lbits = (uint32_t)ch.lbits; ta.t0 = (uint32_t)(ch.cs >> L); ta.L = L; ta.l = l;
     ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
     ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
-    ta.xpat = xpat; ta.use_x = B >= 61 ? 1u : 0u;
     ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
     ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
     ta.b = b; ta.nbins = ch.nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
@@ -1017,15 +999,15 @@ uint64_t window_cap(const Window& w, uint64_t med_lim) {
 }
 
 uint32_t tiles_per_cu(uint32_t L) {
-  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1 + (L == 20 ? sv::kXPatWords : 1)) * 4;
+  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1) * 4;
   return (uint32_t)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / lds));
 }
 
 template <typename E>
 void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::BatchReq* rq, uint32_t nreq, uint32_t nitems,
                        uint32_t* queue, const void* bucket, const uint32_t* bstart, uint32_t b, uint32_t cap, uint32_t l,
-                       uint32_t* tcnt, const uint32_t* xpat) {
-#define SV_TB(LL) sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, queue, bucket, bstart, b, cap, l, tcnt, xpat)
+                       uint32_t* tcnt) {
+#define SV_TB(LL) sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, queue, bucket, bstart, b, cap, l, tcnt)
   switch (L) {
     case 13: SV_TB(13); break;
     case 14: SV_TB(14); break;
@@ -1080,8 +1062,6 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   const uint32_t L = R.L, b = R.b, esz = b <= 16 ? 2 : 4;
   const uint64_t med_lim = 1ull << R.Mlog;
   const uint32_t nw = (uint32_t)W.size();
-  const uint32_t* xpat;
-  STCHK(get_xpattern(c, s, &xpat));
   // per-window layout
   c->h_req.assign(nw, sv::BatchReq());
   c->h_blk.clear();
@@ -1100,7 +1080,7 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, X.B, s, &pat, &per, &patw, &pmask));
     q.pat = pat; q.per = per; q.patw = patw; q.per_G0 = (uint32_t)(X.G0 % per);
-    q.per_tile = (uint32_t)((1ull << L) % per); q.fixmask = pmask; q.use_x = X.B >= 61 ? 1u : 0u;
+    q.per_tile = (uint32_t)((1ull << L) % per); q.fixmask = pmask;
     q.qp_cap = (uint32_t)(pi_upper(std::min<uint64_t>(X.B, med_lim)) + 16);
     q.off_cap = (uint32_t)(pi_upper(X.B) + 16);
     q.QP = reinterpret_cast<uint2*>(qp_tot);       // offsets into the slabs; rebased below
@@ -1200,11 +1180,11 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   const uint32_t* bsp = njobs ? c->bstart.as<uint32_t>() : nullptr;
   if (esz == 2)
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc, xpat);
+      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
     }));
   else
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc, xpat);
+      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
     }));
   if (seg_long)
     STCHK(launch(c, "k_counts_batch", s, [&] {

@@ -41,8 +41,7 @@ def test_small_config_pi_2_22():
     (5, 0, 1, 3), (5, 0, 1, 13), (6, 0, 3, 17), (10, 0, 4, 1000), (11, 0, 16, 3),
     (12, 5, 7, 61), (16, 0, 1, 65535), (20, 0, 2, 65536), (20, 0, 1, 65537),
     (18, 1, 3, 2000), (13, 1000, 9, 200003),
-    # 2^20-bit tiles from 1: with B >= 61 the primes 17..61 come from the extended
-    # patterns, and the primes themselves must stay unmarked
+    # 2^20-bit tiles from 1 with small bounds: the primes themselves stay unmarked
     (20, 0, 1, 61), (20, 0, 1, 60), (20, 0, 3, 1000),
 ])
 def test_edge_cases(case):
