@@ -4,7 +4,8 @@ A request is an interval of Section 1.2.1 at segment size 2^l, (f, n), sieved wi
 B = isqrt(v) (or a given bound).  The server replays an open-loop arrival
 schedule, admits waiting requests first come first served as long as an in-flight
 slot is free and the HBM budget (table + counts + batch scratch) allows, launches
-each admitted group as one sieve_batch on that slot's own context and stream, and
+each admitted group as one sieve_batch (a group of one as the plain per-interval
+call, which costs less) on that slot's own context and stream, and
 retires slots by polling their completion events.  Requests that arrive while
 others are on the GPU join the next group as soon as a slot and memory free up,
 and groups on different slots overlap on the device.  Latency of a request is the
@@ -55,7 +56,13 @@ class GpuExecutor:
             for r in reqs:
                 S, c = self.api.alloc(self.l, r.n)
                 outs.append((r.f, r.n, r.B, S, c))
-            slot["ctx"].batch(self.primes, self.l, outs, tune=self.tune, stream=slot["stream"])
+            if len(outs) == 1:
+                # a group of one (light load): the plain per-interval call has less
+                # fixed cost than a batch of one, with the same result
+                f, n, B, S, c = outs[0]
+                slot["ctx"].sieve(self.l, f, n, B, S, c, tune=self.tune, stream=slot["stream"], primes=self.primes)
+            else:
+                slot["ctx"].batch(self.primes, self.l, outs, tune=self.tune, stream=slot["stream"])
             host_counts = [torch.empty(r.n, dtype=torch.int32, pin_memory=True) for r in reqs]
             for hc, o in zip(host_counts, outs):
                 hc.copy_(o[4], non_blocking=True)
