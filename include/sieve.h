@@ -69,13 +69,16 @@ typedef enum {
  *               of Section 3.2.2.  9 <= wave_log2 <= wheel_log2 <= medium_log2.
  *               Defaults 9 and min(tile_log2-7, medium_log2) (at least 9).
  *   bins_log2   log2 of the number of large-prime buckets per chunk, 8..15.
- *   groups      workgroups of the bucket-fill kernels per chunk, 64..2048
- *               (rounded down to a multiple of ranges); default 1024.  Each takes
- *               a contiguous slice of the large primes of equal estimated work.
- *   ranges      the buckets of a chunk are split into this many ranges of bins
- *               (default 1), each filled by groups/ranges workgroups over all large
- *               primes: fewer bins per workgroup allow larger LDS stages, at the
- *               cost of visiting every large prime once per range.
+ *   groups      workgroups of the bucket-fill kernels, 64..2048; default 1024.
+ *               Each takes a contiguous slice of the large primes of equal
+ *               estimated work.  With ranges given, a chunk's workgroups are split
+ *               over its ranges (groups rounded down to a multiple of ranges);
+ *               by default every range gets groups workgroups.
+ *   ranges      the bins of a chunk are filled in this many ranges (1, 2, 4 or 8;
+ *               0, the default: two for chunks of 1024 bins or more, else one).
+ *               Fewer bins per scatter workgroup leave fewer partly written
+ *               cache lines, at the cost of visiting every large prime once per
+ *               range; the per-bin counts are taken once for the whole chunk.
  *   bin_log2    log2 of one bucket's width in bits, min(tile_log2,16)..tile_log2.
  *               Up to 16 a hit is stored as a 16-bit in-bucket offset, above 16
  *               as a 32-bit one.

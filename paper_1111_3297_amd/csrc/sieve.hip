@@ -35,8 +35,9 @@ thread_local int g_last_hip = 0;
 
 constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
 constexpr uint32_t kGenTile = 20;             // tile of the prime generator
-constexpr uint32_t kRanges = 1;               // minimum bucket ranges per chunk
+constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or more use two bin ranges by default
 constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
+constexpr uint32_t kMaxCountBins = 32768;      // bins of one count job (its LDS histogram: 128 KB)
 
 // Grow-only device buffer.
 struct DevBuf {
@@ -106,11 +107,11 @@ int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
   if (r->b < std::min<uint32_t>(r->L, 16) || r->b > r->L) return SIEVE_E_ARG;
   r->binslog = t->bins_log2 ? t->bins_log2 : std::min<uint32_t>(15, 31 - r->b);
   if (r->binslog < 8 || r->binslog > 15) return SIEVE_E_ARG;
-  r->R = t->ranges ? t->ranges : kRanges;
-  if (r->R != 1 && r->R != 2 && r->R != 4 && r->R != 8) return SIEVE_E_ARG;
+  r->R = t->ranges;                              // 0: chosen per chunk
+  if (r->R != 0 && r->R != 1 && r->R != 2 && r->R != 4 && r->R != 8) return SIEVE_E_ARG;
   r->groups = t->groups ? t->groups : 1024;
   if (r->groups < 64 || r->groups > 2048) return SIEVE_E_ARG;
-  r->groups -= r->groups % r->R;
+  if (r->R) r->groups -= r->groups % r->R;
   return SIEVE_OK;
 }
 
@@ -148,12 +149,12 @@ struct sieve_ctx {
   // scratch
   DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk;
   // batch scratch and the host copies of its tables
-  DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, thr;
+  DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, cjobs, cblk2job, thr;
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk;
   std::vector<uint32_t> h_seg0;
-  std::vector<sv::BucketJob> h_jobs;
-  std::vector<uint32_t> h_blk2job, h_thr;
+  std::vector<sv::BucketJob> h_jobs, h_cjobs;           // scatter jobs (bin ranges), count jobs (whole chunks)
+  std::vector<uint32_t> h_blk2job, h_cblk2job, h_thr;
   // pinned staging for host-to-device table copies; reused only after the
   // previous call's copies have completed (pin_ev)
   void* pin = nullptr;
@@ -175,7 +176,8 @@ struct sieve_ctx {
 sieve_ctx::~sieve_ctx() {
   if (has_last) (void)hipStreamSynchronize(last_stream);
   DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk,
-                    &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &thr, &own.P, &own.cnt};
+                    &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
+                    &own.P, &own.cnt};
   for (DevBuf* b : bufs) b->release();
   for (auto& b : pat) b.release();
   for (auto& e : ev_pool) (void)hipEventDestroy(e);
@@ -466,15 +468,21 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
 void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uint32_t groups, double lo_p, double B,
                 const uint32_t* Ptab, const sv::Plan* plan, const uint32_t* OFF_in, uint32_t* OFF_out,
                 uint32_t gbin_base, std::vector<sv::BucketJob>* jobs, std::vector<uint32_t>* blk2job,
+                std::vector<sv::BucketJob>* cjobs, std::vector<uint32_t>* cblk2job,
                 std::vector<uint32_t>* thr, uint64_t* hg) {
-  uint32_t R = std::max<uint32_t>(ranges, (nbins + sv::kMaxStageBins - 1) / sv::kMaxStageBins);
+  // bin ranges: as given, or by default two for large chunks (a scatter workgroup
+  // with fewer bins leaves fewer partly written lines in L2) and one otherwise; at
+  // least enough for the LDS stages
+  uint32_t R = ranges ? ranges : (nbins >= kAutoRangeBins ? 2u : 1u);
+  R = std::max<uint32_t>(R, (nbins + sv::kMaxStageBins - 1) / sv::kMaxStageBins);
   R = std::min(R, nbins);
   const uint32_t rbins = (nbins + R - 1) / R;
-  // workgroups per range: as given, but no more than one per kHitsPerGroup expected
-  // hits (small jobs would otherwise pay a set-up and a flush per idle workgroup)
+  // workgroups per range (and of the count job): groups / ranges as given, or groups
+  // by default; no more than one per kHitsPerGroup expected hits (small jobs would
+  // otherwise pay a set-up and a flush per idle workgroup)
   const double range_hits = recip_sum_upper(lo_p, B) * (double)rbins * std::ldexp(1.0, (int)b);
-  const uint32_t GR = (uint32_t)std::max<double>(1.0, std::min<double>(std::max<uint32_t>(1, groups / R),
-                                                                       std::ceil(range_hits / kHitsPerGroup)));
+  const uint32_t per_range = ranges ? std::max<uint32_t>(1, groups / R) : groups;
+  const uint32_t GR = (uint32_t)std::max<double>(1.0, std::min<double>(per_range, std::ceil(range_hits / kHitsPerGroup)));
   const uint32_t t0 = (uint32_t)thr->size();
   thr->resize(t0 + GR);
   work_thresholds(lo_p, B, (double)rbins * (double)(1ull << b), GR, thr->data() + t0);
@@ -484,6 +492,20 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
   const double exp_region = recip_sum_upper(lo_p, B) * std::ldexp(1.0, (int)b) / GR;
   uint32_t sbl_cap = 0;
   while ((2u << sbl_cap) * esz <= sv::kMaxStageBytes && (double)(2u << sbl_cap) <= exp_region / 2) ++sbl_cap;
+  // one count job over all bins (each prime visited once) whose histogram rows
+  // (GR x nbins) the range jobs of the scatter read with row stride nbins
+  const uint32_t hg0 = (uint32_t)*hg;
+  {
+    sv::BucketJob C;
+    memset(&C, 0, sizeof C);
+    C.Ptab = Ptab; C.plan = plan; C.OFF_in = OFF_in; C.OFF_out = OFF_out;
+    C.thr = reinterpret_cast<const uint32_t*>((uintptr_t)t0);
+    C.cbits = cbits; C.b = b; C.kb0 = 0; C.rbins = nbins; C.GR = GR;
+    C.block0 = (uint32_t)cblk2job->size(); C.hg = hg0; C.hstride = nbins; C.gbin0 = gbin_base; C.sbl = 1;
+    for (uint32_t q = 0; q < GR; ++q) cblk2job->push_back((uint32_t)cjobs->size());
+    cjobs->push_back(C);
+    *hg += (uint64_t)GR * nbins;
+  }
   for (uint32_t x = 0; x < R; ++x) {
     sv::BucketJob J;
     memset(&J, 0, sizeof J);
@@ -492,9 +514,8 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
     J.Ptab = Ptab; J.plan = plan; J.OFF_in = OFF_in; J.OFF_out = OFF_out;
     J.thr = reinterpret_cast<const uint32_t*>((uintptr_t)t0);   // index into thr, rebased after upload
     J.cbits = cbits; J.b = b; J.rbins = std::min(rbins, nbins - J.kb0); J.update = (x + 1 == R) || (J.kb0 + rbins >= nbins);
-    J.GR = GR; J.block0 = (uint32_t)blk2job->size(); J.hg = (uint32_t)*hg; J.gbin0 = gbin_base + J.kb0;
+    J.GR = GR; J.block0 = (uint32_t)blk2job->size(); J.hg = hg0 + J.kb0; J.hstride = nbins; J.gbin0 = gbin_base + J.kb0;
     J.sbl = sbl_cap;   // an upper bound here; set_stages fits it to the launch's LDS
-    *hg += (uint64_t)GR * J.rbins;
     for (uint32_t q = 0; q < GR; ++q) blk2job->push_back((uint32_t)jobs->size());
     jobs->push_back(J);
     if (J.update) break;
@@ -504,13 +525,14 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
 // Counting sort of the hits of a set of jobs into the bucket array:
 // per-workgroup counts, scan over (bin, workgroup), staged scatter.
 int bucket_fill_jobs(sieve_ctx* c, const sv::BucketJob* djobs, const uint32_t* dblk2job, uint32_t njobs, uint32_t nblocks,
-                     uint32_t gbins, uint32_t max_rbins, uint32_t lds, uint32_t esz, uint32_t cap, hipStream_t s) {
+                     const sv::BucketJob* dcjobs, const uint32_t* dcblk2job, uint32_t ncblocks, uint32_t max_cbins,
+                     uint32_t gbins, uint32_t lds, uint32_t esz, uint32_t cap, hipStream_t s) {
   uint32_t* HG = c->HG.as<uint32_t>();
   uint32_t* bst = c->bstart.as<uint32_t>();
   uint32_t* tot = bst + gbins + 1;
   const uint32_t gb = (gbins + sv::kBinsPerBlock - 1) / sv::kBinsPerBlock;
-  const size_t lc = (size_t)max_rbins * 4, ls = lds;
-  STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count2<<<nblocks, 1024, lc, s>>>(djobs, dblk2job, HG); }));
+  const size_t lc = (size_t)max_cbins * 4, ls = lds;
+  STCHK(launch(c, "k_bucket_count", s, [&] { sv::k_bucket_count2<<<ncblocks, 1024, lc, s>>>(dcjobs, dcblk2job, HG); }));
   STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_jobs<<<gb, 1024, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 0); }));
   STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, gbins, bst); }));
   STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_jobs<<<gb, 1024, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 1); }));
@@ -531,12 +553,24 @@ int bucket_fill_jobs(sieve_ctx* c, const sv::BucketJob* djobs, const uint32_t* d
 int upload_jobs(sieve_ctx* c, hipStream_t s) {
   STCHK(c->jobs.ensure(c->h_jobs.size() * sizeof(sv::BucketJob) + 64));
   STCHK(c->blk2job.ensure(c->h_blk2job.size() * 4 + 64));
+  STCHK(c->cjobs.ensure(c->h_cjobs.size() * sizeof(sv::BucketJob) + 64));
+  STCHK(c->cblk2job.ensure(c->h_cblk2job.size() * 4 + 64));
   STCHK(c->thr.ensure(c->h_thr.size() * 4 + 64));
   for (auto& J : c->h_jobs) J.thr = c->thr.as<uint32_t>() + reinterpret_cast<uintptr_t>(J.thr);
+  for (auto& J : c->h_cjobs) J.thr = c->thr.as<uint32_t>() + reinterpret_cast<uintptr_t>(J.thr);
   STCHK(upload(c, s, c->jobs.p, c->h_jobs.data(), c->h_jobs.size() * sizeof(sv::BucketJob)));
   STCHK(upload(c, s, c->blk2job.p, c->h_blk2job.data(), c->h_blk2job.size() * 4));
+  STCHK(upload(c, s, c->cjobs.p, c->h_cjobs.data(), c->h_cjobs.size() * sizeof(sv::BucketJob)));
+  STCHK(upload(c, s, c->cblk2job.p, c->h_cblk2job.data(), c->h_cblk2job.size() * 4));
   STCHK(upload(c, s, c->thr.p, c->h_thr.data(), c->h_thr.size() * 4));
   return SIEVE_OK;
+}
+
+// Pinned staging bytes upload_jobs needs.
+size_t job_upload_bytes(const sieve_ctx* c) {
+  return pad256(c->h_jobs.size() * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
+         pad256(c->h_cjobs.size() * sizeof(sv::BucketJob)) + pad256(c->h_cblk2job.size() * 4) +
+         pad256(c->h_thr.size() * 4);
 }
 
 // The sieve proper for one request (l, F, NB) with the table pr and bound B.
@@ -562,9 +596,9 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   const uint32_t esz = b <= 16 ? 2 : 4;                        // bytes per bucket entry
   const uint64_t chunk_max = std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits);  // bits per bucket fill
   // every chunk of every launch, with its bucket jobs
-  struct Chunk { uint64_t ls, lbits, cs, cbits; uint32_t nbins, j0, j1, b0, b1, max_rbins, lds; };
+  struct Chunk { uint64_t ls, lbits, cs, cbits; uint32_t nbins, j0, j1, b0, b1, cj0, cb0, cb1, max_rbins, lds; };
   std::vector<Chunk> chunks;
-  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_thr.clear();
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_cjobs.clear(); c->h_cblk2job.clear(); c->h_thr.clear();
   uint64_t hg_max = 0, cap = 0, pad_max = 0;
   uint32_t nbins_max = 0;
   if (large) {
@@ -580,25 +614,29 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       ch.ls = ls; ch.lbits = lbits; ch.cs = cs; ch.cbits = std::min<uint64_t>(chunk_max, lbits - cs);
       ch.nbins = (uint32_t)((ch.cbits + (1ull << b) - 1) >> b);
       ch.j0 = (uint32_t)c->h_jobs.size(); ch.b0 = (uint32_t)c->h_blk2job.size();
+      ch.cj0 = (uint32_t)c->h_cjobs.size(); ch.cb0 = (uint32_t)c->h_cblk2job.size();
       ch.max_rbins = 1;
       if (large) {
         uint64_t hg = 0;
         const uint32_t* oin = c->OFF.as<uint32_t>() + (size_t)off_cur * nL_ub;
         uint32_t* oout = c->OFF.as<uint32_t>() + (size_t)(1 - off_cur) * nL_ub;
-        const size_t jb = c->h_jobs.size();
+        const size_t jb = c->h_jobs.size(), cjb = c->h_cjobs.size();
         chunk_jobs(ch.nbins, (uint32_t)ch.cbits, b, R.R, R.groups, (double)med_lim, (double)B, pr->P.as<uint32_t>(),
-                   plan, oin, oout, 0, &c->h_jobs, &c->h_blk2job, &c->h_thr, &hg);
+                   plan, oin, oout, 0, &c->h_jobs, &c->h_blk2job, &c->h_cjobs, &c->h_cblk2job, &c->h_thr, &hg);
         for (size_t k = jb; k < c->h_jobs.size(); ++k) {   // block numbers and job indices relative to the chunk
           c->h_jobs[k].block0 -= ch.b0;
           ch.max_rbins = std::max(ch.max_rbins, c->h_jobs[k].rbins);
         }
+        for (size_t k = cjb; k < c->h_cjobs.size(); ++k) c->h_cjobs[k].block0 -= ch.cb0;
         pad_max = std::max(pad_max, set_stages(c->h_jobs, jb, c->h_jobs.size(), esz, &ch.lds));
         for (size_t k = ch.b0; k < c->h_blk2job.size(); ++k) c->h_blk2job[k] -= ch.j0;
+        for (size_t k = ch.cb0; k < c->h_cblk2job.size(); ++k) c->h_cblk2job[k] -= ch.cj0;
         hg_max = std::max(hg_max, hg);
         nbins_max = std::max(nbins_max, ch.nbins);
         off_cur ^= 1u;
       }
       ch.j1 = (uint32_t)c->h_jobs.size(); ch.b1 = (uint32_t)c->h_blk2job.size();
+      ch.cb1 = (uint32_t)c->h_cblk2job.size();
       chunks.push_back(ch);
     }
   }
@@ -608,8 +646,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     STCHK(c->HG.ensure(hg_max * 4 + 64));
     STCHK(c->bstart.ensure(((size_t)2 * nbins_max + 2) * 4));   // bin_start, then bin totals
     STCHK(c->bucket.ensure(cap * esz));
-    STCHK(pin_begin(c, pad256(c->h_jobs.size() * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
-                           pad256(c->h_thr.size() * 4)));
+    STCHK(pin_begin(c, job_upload_bytes(c)));
     STCHK(upload_jobs(c, s));
     STCHK(pin_end(c, s));
   }
@@ -622,6 +659,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   const uint32_t patG_step = (uint32_t)((1ull << L) % per);
   const sv::BucketJob* djobs = c->jobs.as<sv::BucketJob>();
   const uint32_t* dblk = c->blk2job.as<uint32_t>();
+  const sv::BucketJob* dcjobs = c->cjobs.as<sv::BucketJob>();
+  const uint32_t* dcblk = c->cblk2job.as<uint32_t>();
   uint64_t cur_ls = ~0ull;
   for (const Chunk& ch : chunks) {
     const uint64_t G0 = F + ch.ls;
@@ -636,8 +675,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     const uint64_t psq = isqrt_u64(2 * G0 + 1);
     const uint32_t ntiles = (uint32_t)((ch.cbits + (1ull << L) - 1) >> L);
     if (large)
-      STCHK(bucket_fill_jobs(c, djobs + ch.j0, dblk + ch.b0, ch.j1 - ch.j0, ch.b1 - ch.b0, ch.nbins, ch.max_rbins, ch.lds,
-                             esz, (uint32_t)cap, s));
+      STCHK(bucket_fill_jobs(c, djobs + ch.j0, dblk + ch.b0, ch.j1 - ch.j0, ch.b1 - ch.b0, dcjobs + ch.cj0, dcblk + ch.cb0,
+                             ch.cb1 - ch.cb0, ch.nbins, ch.nbins, ch.lds, esz, (uint32_t)cap, s));
     sv::TileArgs ta;
     memset(&ta, 0, sizeof ta);
     ta.G0 = G0; ta.lbits = (uint32_t)ch.lbits; ta.t0 = (uint32_t)(ch.cs >> L); ta.L = L; ta.l = l;
@@ -899,10 +938,11 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   const uint32_t b = R.b, esz = b <= 16 ? 2 : 4;
   const uint64_t cbits = std::min<uint64_t>(std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits), lbits);
   const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
-  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_thr.clear();
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_cjobs.clear(); c->h_cblk2job.clear(); c->h_thr.clear();
   uint64_t hg = 0;
   chunk_jobs(nbins, (uint32_t)cbits, b, R.R, R.groups, (double)med_lim, (double)B, c->own.P.as<uint32_t>(), plan,
-             c->OFF.as<uint32_t>(), c->OFF.as<uint32_t>() + tab_ub, 0, &c->h_jobs, &c->h_blk2job, &c->h_thr, &hg);
+             c->OFF.as<uint32_t>(), c->OFF.as<uint32_t>() + tab_ub, 0, &c->h_jobs, &c->h_blk2job, &c->h_cjobs,
+             &c->h_cblk2job, &c->h_thr, &hg);
   uint32_t max_rbins = 1;
   for (auto& J : c->h_jobs) max_rbins = std::max(max_rbins, J.rbins);
   STCHK(c->HG.ensure(hg * 4 + 64));
@@ -915,12 +955,13 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
   STCHK(c->bucket.ensure(cap * esz));
   STCHK(ensure_err(c, s));
-  STCHK(pin_begin(c, pad256(c->h_jobs.size() * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
-                         pad256(c->h_thr.size() * 4)));
+  STCHK(pin_begin(c, job_upload_bytes(c)));
   STCHK(upload_jobs(c, s));
   STCHK(pin_end(c, s));
+  (void)max_rbins;
   STCHK(bucket_fill_jobs(c, c->jobs.as<sv::BucketJob>(), c->blk2job.as<uint32_t>(), (uint32_t)c->h_jobs.size(),
-                         (uint32_t)c->h_blk2job.size(), nbins, max_rbins, lds, esz, (uint32_t)cap, s));
+                         (uint32_t)c->h_blk2job.size(), c->cjobs.as<sv::BucketJob>(), c->cblk2job.as<uint32_t>(),
+                         (uint32_t)c->h_cblk2job.size(), nbins, nbins, lds, esz, (uint32_t)cap, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<uint32_t> bs(nbins + 1);
   HIPCHK(hipMemcpy(bs.data(), c->bstart.p, (nbins + 1) * 4, hipMemcpyDeviceToHost));
@@ -1109,7 +1150,8 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     work[w] = hits + 2.0 * (double)pi_upper(q.B);
     work_tot += work[w];
   }
-  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_thr.clear();
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_cjobs.clear(); c->h_cblk2job.clear(); c->h_thr.clear();
+  uint32_t max_cbins = 1;
   for (uint32_t w = 0; w < nw; ++w) {
     const sv::BatchReq& q = c->h_req[w];
     if (!q.nbins) continue;
@@ -1117,10 +1159,11 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     const size_t jb = c->h_jobs.size();
     chunk_jobs(q.nbins, q.lbits, b, R.R, groups, (double)med_lim, (double)q.B, pr->P.as<uint32_t>(),
                reinterpret_cast<const sv::Plan*>((uintptr_t)w), reinterpret_cast<const uint32_t*>((uintptr_t)w), nullptr,
-               q.bin_base, &c->h_jobs, &c->h_blk2job, &c->h_thr, &hg_tot);
+               q.bin_base, &c->h_jobs, &c->h_blk2job, &c->h_cjobs, &c->h_cblk2job, &c->h_thr, &hg_tot);
     for (size_t k = jb; k < c->h_jobs.size(); ++k) max_rbins = std::max(max_rbins, c->h_jobs[k].rbins);
+    max_cbins = std::max(max_cbins, q.nbins);
   }
-  if (max_rbins > sv::kMaxStageBins) return SIEVE_E_NOMEM;
+  if (max_rbins > sv::kMaxStageBins || max_cbins > kMaxCountBins) return SIEVE_E_NOMEM;
   uint32_t lds = 0;
   cap_tot += set_stages(c->h_jobs, 0, c->h_jobs.size(), esz, &lds);
   if (cap_tot >= 0xFFFFFFFFull || hg_tot >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
@@ -1138,17 +1181,17 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     q.QP = c->Q0.as<uint2>() + reinterpret_cast<uintptr_t>(q.QP);
     q.OFF = c->OFF.as<uint32_t>() + reinterpret_cast<uintptr_t>(q.OFF);
   }
-  for (sv::BucketJob& J : c->h_jobs) {   // one chunk per request: no next-chunk offsets
-    const uintptr_t w = reinterpret_cast<uintptr_t>(J.plan);
-    J.plan = &dreq[w].plan;
-    J.OFF_in = c->h_req[w].OFF;
-    J.OFF_out = nullptr;
-    J.update = 0;
-  }
+  for (auto* list : {&c->h_jobs, &c->h_cjobs})
+    for (sv::BucketJob& J : *list) {   // one chunk per request: no next-chunk offsets
+      const uintptr_t w = reinterpret_cast<uintptr_t>(J.plan);
+      J.plan = &dreq[w].plan;
+      J.OFF_in = c->h_req[w].OFF;
+      J.OFF_out = nullptr;
+      J.update = 0;
+    }
   const uint32_t njobs = (uint32_t)c->h_jobs.size();
   STCHK(pin_begin(c, pad256(nw * sizeof(sv::BatchReq)) + pad256(c->h_blk.size() * sizeof(uint2)) + pad256(nw * 4) +
-                         pad256(njobs * sizeof(sv::BucketJob)) + pad256(c->h_blk2job.size() * 4) +
-                         pad256(c->h_thr.size() * 4)));
+                         job_upload_bytes(c)));
   STCHK(upload(c, s, c->b_req.p, c->h_req.data(), nw * sizeof(sv::BatchReq)));
   STCHK(upload(c, s, c->b_blk.p, c->h_blk.data(), c->h_blk.size() * sizeof(uint2)));
   STCHK(upload(c, s, c->b_seg0.p, c->h_seg0.data(), nw * 4));
@@ -1170,7 +1213,8 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     STCHK(c->bucket.ensure(cap_tot * esz));
     cap32 = (uint32_t)cap_tot;
     STCHK(bucket_fill_jobs(c, c->jobs.as<sv::BucketJob>(), c->blk2job.as<uint32_t>(), njobs,
-                           (uint32_t)c->h_blk2job.size(), gbins, max_rbins, lds, esz, cap32, s));
+                           (uint32_t)c->h_blk2job.size(), c->cjobs.as<sv::BucketJob>(), c->cblk2job.as<uint32_t>(),
+                           (uint32_t)c->h_cblk2job.size(), max_cbins, gbins, lds, esz, cap32, s));
   }
   int ncu = 0;
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
