@@ -143,6 +143,7 @@ struct KernelTime {
 struct sieve_ctx {
   std::mutex mu;
   int device = 0;
+  uint32_t ncu = 0;                 // compute units of the device
   hipStream_t last_stream = nullptr;
   bool has_last = false;
   hipEvent_t done = nullptr;
@@ -376,18 +377,27 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
   return SIEVE_OK;
 }
 
-// Launches the tile kernel instantiated for tile size 2^L and entry type E.
+// Workgroups of 1024 lanes that one compute unit holds at tile size 2^L.
+uint32_t tiles_per_cu(uint32_t L) {
+  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1) * 4;
+  return (uint32_t)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / lds));
+}
+
+// Launches the tile kernel instantiated for tile size 2^L and entry type E over
+// ta.ntiles tiles: one workgroup per resident slot, each taking a run of
+// consecutive tiles.
 template <typename E>
-void launch_tile(uint32_t L, uint32_t ntiles, hipStream_t s, const sv::TileArgs& ta) {
+void launch_tile(const sieve_ctx* c, uint32_t L, hipStream_t s, sv::TileArgs ta) {
+  const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(ta.ntiles, c->ncu * tiles_per_cu(L)));
   switch (L) {
-    case 13: sv::k_tile<E, 13><<<ntiles, 1024, 0, s>>>(ta); break;
-    case 14: sv::k_tile<E, 14><<<ntiles, 1024, 0, s>>>(ta); break;
-    case 15: sv::k_tile<E, 15><<<ntiles, 1024, 0, s>>>(ta); break;
-    case 16: sv::k_tile<E, 16><<<ntiles, 1024, 0, s>>>(ta); break;
-    case 17: sv::k_tile<E, 17><<<ntiles, 1024, 0, s>>>(ta); break;
-    case 18: sv::k_tile<E, 18><<<ntiles, 1024, 0, s>>>(ta); break;
-    case 19: sv::k_tile<E, 19><<<ntiles, 1024, 0, s>>>(ta); break;
-    default: sv::k_tile<E, 20><<<ntiles, 1024, 0, s>>>(ta); break;
+    case 13: sv::k_tile<E, 13><<<g, 1024, 0, s>>>(ta); break;
+    case 14: sv::k_tile<E, 14><<<g, 1024, 0, s>>>(ta); break;
+    case 15: sv::k_tile<E, 15><<<g, 1024, 0, s>>>(ta); break;
+    case 16: sv::k_tile<E, 16><<<g, 1024, 0, s>>>(ta); break;
+    case 17: sv::k_tile<E, 17><<<g, 1024, 0, s>>>(ta); break;
+    case 18: sv::k_tile<E, 18><<<g, 1024, 0, s>>>(ta); break;
+    case 19: sv::k_tile<E, 19><<<g, 1024, 0, s>>>(ta); break;
+    default: sv::k_tile<E, 20><<<g, 1024, 0, s>>>(ta); break;
   }
 }
 
@@ -420,7 +430,8 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
     sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
     STCHK(launch(c, "k_plan", s, [&] {
-      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, 1ull << 9, 1ull << 16, 1ull << 17, nbase_ub, gplan);
+      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, 1ull << 9, 1ull << 16, 1ull << 17, 1ull << (kGenTile - 3),
+                                 nbase_ub, gplan);
     }));
     // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
     // 2^15-bit count segments (the extra bits are masked off by the compaction)
@@ -444,12 +455,12 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     STCHK(get_pattern(c, rb, s, &pat, &per, &patw, &pmask));
     sv::TileArgs ta;
     memset(&ta, 0, sizeof ta);
-    ta.G0 = 0; ta.lbits = (uint32_t)gbits; ta.t0 = 0; ta.L = L; ta.l = gl;
+    ta.G0 = 0; ta.lbits = (uint32_t)gbits; ta.t0 = 0; ta.ntiles = ntiles; ta.L = L; ta.l = gl;
     ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = 0; ta.per_tile = (uint32_t)((1ull << L) % per);
-    ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
+    ta.fixmask = pmask; ta.P = base; ta.QP = c->Q0.as<uint2>();
     ta.plan = gplan; ta.psq = 1; ta.has_large = 0; ta.b = 16;
     ta.S = gS; ta.counts = gcounts; ta.count_atomic = 0;
-    STCHK(launch(c, "k_tile[gen]", s, [&] { launch_tile<uint16_t>(L, ntiles, s, ta); }));
+    STCHK(launch(c, "k_tile[gen]", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
     STCHK(launch(c, "k_compact_count", s, [&] {
       sv::k_compact_count<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk);
     }));
@@ -583,7 +594,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
     sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, wave_lim, wheel_lim, med_lim,
-                               (uint32_t)tab_ub, plan);
+                               1ull << (L - 3), (uint32_t)tab_ub, plan);
   }));
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
   STCHK(c->Q0.ensure(med_ub * 8 + 64));
@@ -679,17 +690,17 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
                              ch.cb1 - ch.cb0, ch.nbins, ch.nbins, ch.lds, esz, (uint32_t)cap, s));
     sv::TileArgs ta;
     memset(&ta, 0, sizeof ta);
-    ta.G0 = G0; ta.lbits = (uint32_t)ch.lbits; ta.t0 = (uint32_t)(ch.cs >> L); ta.L = L; ta.l = l;
+    ta.G0 = G0; ta.lbits = (uint32_t)ch.lbits; ta.t0 = (uint32_t)(ch.cs >> L); ta.ntiles = ntiles; ta.L = L; ta.l = l;
     ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
-    ta.fixmask = pmask; ta.QP = c->Q0.as<uint2>();
+    ta.fixmask = pmask; ta.P = pr->P.as<uint32_t>(); ta.QP = c->Q0.as<uint2>();
     ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
     ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
     ta.b = b; ta.nbins = ch.nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
     ta.S = S + (ch.ls >> 5); ta.counts = counts + (ch.ls >> l); ta.count_atomic = count_atomic ? 1 : 0;
     if (esz == 2)
-      STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(L, ntiles, s, ta); }));
+      STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
     else
-      STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(L, ntiles, s, ta); }));
+      STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(c, L, s, ta); }));
   }
   return SIEVE_OK;
 }
@@ -698,6 +709,11 @@ int begin(sieve_ctx* c, hipStream_t s) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   c->device = dev;
+  if (!c->ncu) {
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    c->ncu = (uint32_t)std::max(ncu, 1);
+  }
   STCHK(set_lds_limits());
   if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
   return SIEVE_OK;
@@ -929,7 +945,7 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 1ull << R.Wlog, 1ull << R.Blog,
-                             med_lim, (uint32_t)tab_ub, plan);
+                             med_lim, 1ull << (R.L - 3), (uint32_t)tab_ub, plan);
   STCHK(c->Q0.ensure(tab_ub * 8 + 64));
   STCHK(c->OFF.ensure(2 * tab_ub * 4 + 64));
   const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB);
@@ -1037,11 +1053,6 @@ int batch_windows(const sieve_primes* pr, uint32_t l, const sieve_req* reqs, siz
 uint64_t window_cap(const Window& w, uint64_t med_lim) {
   const double rs = recip_sum_upper((double)med_lim, (double)w.B);
   return (uint64_t)(1.02 * rs * (double)w.lbits) + pi_upper(w.B) + 4096;
-}
-
-uint32_t tiles_per_cu(uint32_t L) {
-  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1) * 4;
-  return (uint32_t)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / lds));
 }
 
 template <typename E>

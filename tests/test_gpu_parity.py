@@ -103,6 +103,15 @@ def test_multi_chunk_and_bucket_path():
                tune={"tile_log2": 17, "medium_log2": 14, "bins_log2": 8, "bin_log2": 17, "groups": 80})
 
 
+def test_carried_rows_across_tiles():
+    # more tiles than workgroups, so each workgroup carries the next-hit offsets of
+    # the largest medium primes from tile to tile; primes above sqrt(u) start at p^2
+    # inside the interval (beyond a workgroup's first tile for some of them)
+    check_case(20, (4 * 10**10) >> 21, 600, 300007)
+    # tiles of eight segments with a ragged last tile
+    check_case(17, (10**11) >> 18, 4801, 250000, tune={"tile_log2": 20})
+
+
 def test_prime_table_matches_oracle():
     import torch
     from paper_1111_3297_amd import api
