@@ -362,7 +362,7 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
   uint32_t m = 0, P = 1;
   for (int i = 0; i < 5; ++i)
     if (small[i] <= B) { m |= 1u << i; P *= small[i]; }
-  const uint32_t nw = (P + 64 + 31) / 32;
+  const uint32_t nw = (P + 160 + 31) / 32;   // one period plus the 128-bit windows that start in it
   if (!c->pat_words[m]) {
     STCHK(c->pat[m].ensure((size_t)nw * 4));
     STCHK(launch(c, "k_pattern", s, [&] {
