@@ -108,6 +108,8 @@ def test_carried_rows_across_tiles():
     # the largest medium primes from tile to tile; primes above sqrt(u) start at p^2
     # inside the interval (beyond a workgroup's first tile for some of them)
     check_case(20, (4 * 10**10) >> 21, 600, 300007)
+    # from 1: p^2 starts of every carried class fall inside later tiles of the runs
+    check_case(20, 0, 600, 300007)
     # tiles of eight segments with a ragged last tile
     check_case(17, (10**11) >> 18, 4801, 250000, tune={"tile_log2": 20})
 
