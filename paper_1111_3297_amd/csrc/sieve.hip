@@ -35,6 +35,7 @@ thread_local int g_last_hip = 0;
 
 constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
 constexpr uint32_t kGenTile = 20;             // tile of the prime generator
+constexpr uint32_t kBatchRun = 4;             // consecutive tiles per batch work item
 constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or more use two bin ranges by default
 constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
 constexpr uint32_t kMaxCountBins = 32768;      // bins of one count job (its LDS histogram: 128 KB)
@@ -1057,9 +1058,10 @@ uint64_t window_cap(const Window& w, uint64_t med_lim) {
 
 template <typename E>
 void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::BatchReq* rq, uint32_t nreq, uint32_t nitems,
-                       uint32_t* queue, const void* bucket, const uint32_t* bstart, uint32_t b, uint32_t cap, uint32_t l,
-                       uint32_t* tcnt) {
-#define SV_TB(LL) sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, queue, bucket, bstart, b, cap, l, tcnt)
+                       uint32_t* queue, const uint32_t* P, const void* bucket, const uint32_t* bstart, uint32_t b,
+                       uint32_t cap, uint32_t l, uint32_t* tcnt) {
+#define SV_TB(LL) \
+  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, kBatchRun, queue, P, bucket, bstart, b, cap, l, tcnt)
   switch (L) {
     case 13: SV_TB(13); break;
     case 14: SV_TB(14); break;
@@ -1127,7 +1129,7 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     memset(&q, 0, sizeof q);
     q.G0 = X.G0; q.B = X.B; q.lbits = X.lbits;
     q.ntiles = (X.lbits + (1u << L) - 1) >> L;
-    q.item0 = items; items += q.ntiles;
+    q.item0 = items; items += (q.ntiles + kBatchRun - 1) / kBatchRun;
     q.psq = (uint32_t)std::min<uint64_t>(isqrt_u64(2 * X.G0 + 1), 0xFFFFFFFFull);
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, X.B, s, &pat, &per, &patw, &pmask));
@@ -1211,7 +1213,7 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<1, 64, 0, s>>>(c->b_queue.as<uint32_t>(), 16, 0); }));
   STCHK(launch(c, "k_plan_batch", s, [&] {
     sv::k_plan_batch<<<(nw + 63) / 64, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), dreq, nw,
-                                                   1ull << R.Wlog, 1ull << R.Blog, med_lim);
+                                                   1ull << R.Wlog, 1ull << R.Blog, med_lim, 1ull << (L - 3));
   }));
   const uint32_t nblk = (uint32_t)c->h_blk.size();
   STCHK(launch(c, "k_offsets_batch", s, [&] {
@@ -1235,11 +1237,13 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   const uint32_t* bsp = njobs ? c->bstart.as<uint32_t>() : nullptr;
   if (esz == 2)
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
+      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), bk, bsp,
+                                  b, cap32, l, tc);
     }));
   else
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), bk, bsp, b, cap32, l, tc);
+      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), bk, bsp,
+                                  b, cap32, l, tc);
     }));
   if (seg_long)
     STCHK(launch(c, "k_counts_batch", s, [&] {
