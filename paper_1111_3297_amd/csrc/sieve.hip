@@ -163,7 +163,7 @@ struct sieve_ctx {
   size_t pin_bytes = 0, pin_used = 0;
   hipEvent_t pin_ev = nullptr;
   bool pin_pending = false;
-  DevBuf pat[32];
+  DevBuf pat[32], xpat;
   uint32_t pat_words[32] = {0};
   sieve_primes own;  // table built by sieve_init / sieve_ctx_sieve
   // timing
@@ -361,13 +361,17 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
                 uint32_t* words, uint32_t* mask) {
   static const uint32_t small[5] = {3, 5, 7, 11, 13};
   uint32_t m = 0, P = 1;
+  sv::PatPrimes pp;
+  memset(&pp, 0, sizeof pp);
   for (int i = 0; i < 5; ++i)
-    if (small[i] <= B) { m |= 1u << i; P *= small[i]; }
-  const uint32_t nw = (P + 160 + 31) / 32;   // one period plus the 128-bit windows that start in it
+    if (small[i] <= B) { m |= 1u << i; P *= small[i]; pp.p[pp.n++] = small[i]; }
+  // one period plus the wrap-around of a wave block starting anywhere in it, in
+  // whole 16-byte groups
+  const uint32_t nw = ((P + sv::kPatWrapBits + 31) / 32 + 3) & ~3u;
   if (!c->pat_words[m]) {
     STCHK(c->pat[m].ensure((size_t)nw * 4));
     STCHK(launch(c, "k_pattern", s, [&] {
-      sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->pat[m].as<uint32_t>(), P, m, nw);
+      sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->pat[m].as<uint32_t>(), P, pp, nw);
     }));
     c->pat_words[m] = nw;
   }
@@ -378,9 +382,37 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
   return SIEVE_OK;
 }
 
+// The patterns of 17*19*23, 29*31*37 and 41*43*47 (built once per context).
+int get_xpattern(sieve_ctx* c, hipStream_t s, const uint32_t** xpat) {
+  if (!c->xpat.p) {
+    STCHK(c->xpat.ensure((size_t)sv::kXWordsAll * 4));
+    static const uint32_t sets[3][3] = {{17, 19, 23}, {29, 31, 37}, {41, 43, 47}};
+    for (int i = 0; i < 3; ++i) {
+      sv::PatPrimes pp;
+      memset(&pp, 0, sizeof pp);
+      for (int k = 0; k < 3; ++k) pp.p[k] = sets[i][k];
+      pp.n = 3;
+      const uint32_t end = i < 2 ? sv::kXOff[i + 1] : sv::kXWordsAll;
+      const uint32_t nw = end - sv::kXOff[i];
+      if (nw < (sv::kXPer[i] + sv::kPatWrapBits + 31) / 32) return SIEVE_E_HIP;   // layout constants
+      STCHK(launch(c, "k_pattern", s, [&] {
+        sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->xpat.as<uint32_t>() + sv::kXOff[i], sv::kXPer[i], pp, nw);
+      }));
+    }
+  }
+  *xpat = c->xpat.as<uint32_t>();
+  return SIEVE_OK;
+}
+
+// 17..47 come from patterns when every one of them sieves, the tile is 2^20 bits
+// and the write-out takes four words per lane (segments of at least 2^13 bits, or
+// tiles inside a segment).
+bool use_xpat(uint64_t B, uint32_t L, uint32_t l) { return B >= 47 && L == 20 && (L < l || l >= 13); }
+
 // Workgroups of 1024 lanes that one compute unit holds at tile size 2^L.
 uint32_t tiles_per_cu(uint32_t L) {
-  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1) * 4;
+  const size_t lds = ((size_t)1 << (L - 3)) + (sv::kPatWordsMax + sv::kSegSlotsMax + 1) * 4 +
+                     (L == 20 ? sv::kXWordsAll : 4) * 4;
   return (uint32_t)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / lds));
 }
 
@@ -431,8 +463,8 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
     sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
     STCHK(launch(c, "k_plan", s, [&] {
-      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, 1ull << 9, 1ull << 16, 1ull << 17, 1ull << (kGenTile - 3),
-                                 nbase_ub, gplan);
+      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, use_xpat(rb, kGenTile, 15) ? 53 : 17, 1ull << 9, 1ull << 16,
+                                 1ull << 17, 1ull << (kGenTile - 3), nbase_ub, gplan);
     }));
     // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
     // 2^15-bit count segments (the extra bits are masked off by the compaction)
@@ -459,6 +491,8 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     ta.G0 = 0; ta.lbits = (uint32_t)gbits; ta.t0 = 0; ta.ntiles = ntiles; ta.L = L; ta.l = gl;
     ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = 0; ta.per_tile = (uint32_t)((1ull << L) % per);
     ta.fixmask = pmask; ta.P = base; ta.QP = c->Q0.as<uint2>();
+    ta.xon = use_xpat(rb, L, gl) ? 1u : 0u;
+    if (ta.xon) STCHK(get_xpattern(c, s, &ta.xpat));
     ta.plan = gplan; ta.psq = 1; ta.has_large = 0; ta.b = 16;
     ta.S = gS; ta.counts = gcounts; ta.count_atomic = 0;
     STCHK(launch(c, "k_tile[gen]", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
@@ -594,8 +628,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
-    sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, wave_lim, wheel_lim, med_lim,
-                               1ull << (L - 3), (uint32_t)tab_ub, plan);
+    sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, use_xpat(B, L, l) ? 53 : 17, wave_lim,
+                               wheel_lim, med_lim, 1ull << (L - 3), (uint32_t)tab_ub, plan);
   }));
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
   STCHK(c->Q0.ensure(med_ub * 8 + 64));
@@ -694,6 +728,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     ta.G0 = G0; ta.lbits = (uint32_t)ch.lbits; ta.t0 = (uint32_t)(ch.cs >> L); ta.ntiles = ntiles; ta.L = L; ta.l = l;
     ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_G0 = (uint32_t)(G0 % per); ta.per_tile = patG_step;
     ta.fixmask = pmask; ta.P = pr->P.as<uint32_t>(); ta.QP = c->Q0.as<uint2>();
+    ta.xon = use_xpat(B, L, l) ? 1u : 0u;
+    if (ta.xon) STCHK(get_xpattern(c, s, &ta.xpat));
     ta.plan = plan; ta.psq = (uint32_t)std::min<uint64_t>(psq, 0xFFFFFFFFull);
     ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
     ta.b = b; ta.nbins = ch.nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
@@ -945,8 +981,8 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   const uint64_t tab_ub = pi_upper(B);
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
-  sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 1ull << R.Wlog, 1ull << R.Blog,
-                             med_lim, 1ull << (R.L - 3), (uint32_t)tab_ub, plan);
+  sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 17, 1ull << R.Wlog,
+                             1ull << R.Blog, med_lim, 1ull << (R.L - 3), (uint32_t)tab_ub, plan);
   STCHK(c->Q0.ensure(tab_ub * 8 + 64));
   STCHK(c->OFF.ensure(2 * tab_ub * 4 + 64));
   const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB);
@@ -1058,10 +1094,11 @@ uint64_t window_cap(const Window& w, uint64_t med_lim) {
 
 template <typename E>
 void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::BatchReq* rq, uint32_t nreq, uint32_t nitems,
-                       uint32_t* queue, const uint32_t* P, const void* bucket, const uint32_t* bstart, uint32_t b,
-                       uint32_t cap, uint32_t l, uint32_t* tcnt) {
-#define SV_TB(LL) \
-  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, kBatchRun, queue, P, bucket, bstart, b, cap, l, tcnt)
+                       uint32_t* queue, const uint32_t* P, const uint32_t* xpat, const void* bucket,
+                       const uint32_t* bstart, uint32_t b, uint32_t cap, uint32_t l, uint32_t* tcnt) {
+#define SV_TB(LL)                                                                                                  \
+  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, kBatchRun, queue, P, xpat, bucket, bstart, b, cap, \
+                                                l, tcnt)
   switch (L) {
     case 13: SV_TB(13); break;
     case 14: SV_TB(14); break;
@@ -1122,6 +1159,7 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   c->h_seg0.assign(nw, 0);
   uint64_t qp_tot = 0, off_tot = 0, cap_tot = 0, hg_tot = 0;
   uint32_t items = 0, gbins = 0, tcnt = 0, seg_tot = 0, max_rbins = 1;
+  const uint32_t* xpat = nullptr;
   const bool seg_long = L < l;
   for (uint32_t w = 0; w < nw; ++w) {
     const Window& X = W[w];
@@ -1135,6 +1173,8 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     STCHK(get_pattern(c, X.B, s, &pat, &per, &patw, &pmask));
     q.pat = pat; q.per = per; q.patw = patw; q.per_G0 = (uint32_t)(X.G0 % per);
     q.per_tile = (uint32_t)((1ull << L) % per); q.fixmask = pmask;
+    q.xon = use_xpat(X.B, L, l) ? 1u : 0u;
+    if (q.xon && !xpat) STCHK(get_xpattern(c, s, &xpat));
     q.qp_cap = (uint32_t)(pi_upper(std::min<uint64_t>(X.B, med_lim)) + 16);
     q.off_cap = (uint32_t)(pi_upper(X.B) + 16);
     q.QP = reinterpret_cast<uint2*>(qp_tot);       // offsets into the slabs; rebased below
@@ -1237,12 +1277,12 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   const uint32_t* bsp = njobs ? c->bstart.as<uint32_t>() : nullptr;
   if (esz == 2)
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), bk, bsp,
+      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
                                   b, cap32, l, tc);
     }));
   else
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), bk, bsp,
+      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
                                   b, cap32, l, tc);
     }));
   if (seg_long)
