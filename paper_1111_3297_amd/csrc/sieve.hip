@@ -33,7 +33,7 @@ thread_local int g_last_hip = 0;
     if (s_ != SIEVE_OK) return s_;  \
   } while (0)
 
-constexpr uint64_t kLaunchBits = 1ull << 31;  // offsets of one launch fit 32 bits
+constexpr uint64_t kLaunchBits = sv::kWinBits;  // offsets of one launch window fit 32 bits
 constexpr uint32_t kGenTile = 20;             // tile of the prime generator
 constexpr uint32_t kBatchRun = 4;             // consecutive tiles per batch work item
 constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or more use two bin ranges by default
@@ -463,7 +463,7 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
     sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
     STCHK(launch(c, "k_plan", s, [&] {
-      sv::k_plan<<<1, 1, 0, s>>>(base, base_cnt, rb, use_xpat(rb, kGenTile, 15) ? 53 : 17, 1ull << 9, 1ull << 16,
+      sv::k_plan<<<1, 64, 0, s>>>(base, base_cnt, rb, use_xpat(rb, kGenTile, 15) ? 53 : 17, 1ull << 9, 1ull << 16,
                                  1ull << 17, 1ull << (kGenTile - 3), nbase_ub, gplan);
     }));
     // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
@@ -482,7 +482,7 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     uint32_t* gcounts = gblk + nblk + 32;
     STCHK(c->Q0.ensure(pi_upper(65536) * 8));
     STCHK(launch(c, "k_offsets", s, [&] {
-      sv::k_offsets<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, gplan, 0, gbits, c->Q0.as<uint2>(), nullptr);
+      sv::k_offsets<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, gplan, 0, gbits, c->Q0.as<uint2>(), nullptr, 0);
     }));
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, rb, s, &pat, &per, &patw, &pmask));
@@ -628,7 +628,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
-    sv::k_plan<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, use_xpat(B, L, l) ? 53 : 17, wave_lim,
+    sv::k_plan<<<1, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, use_xpat(B, L, l) ? 53 : 17, wave_lim,
                                wheel_lim, med_lim, 1ull << (L - 3), (uint32_t)tab_ub, plan);
   }));
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
@@ -638,6 +638,49 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   if (large) STCHK(c->OFF.ensure(2 * nL_ub * 4 + 64));           // in / out halves
   const uint32_t* pat; uint32_t per, patw, pmask;
   STCHK(get_pattern(c, B, s, &pat, &per, &patw, &pmask));
+  const uint32_t nwin = (uint32_t)((NB + kLaunchBits - 1) / kLaunchBits);
+  if (!large && nwin <= sv::kMaxWins) {
+    // medium primes only: one offsets launch and one tile launch for all windows
+    STCHK(c->Q0.ensure((size_t)nwin * med_ub * 8 + 64));
+    STCHK(ensure_err(c, s));
+    const bool count_atomic = L < l;
+    if (count_atomic) {
+      const uint64_t n = NB >> l;
+      STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(counts, n, 0); }));
+    }
+    STCHK(launch(c, "k_offsets", s, [&] {
+      sv::k_offsets<<<dim3((uint32_t)((tab_ub + 255) / 256), nwin), 256, 0, s>>>(
+          pr->P.as<uint32_t>(), plan, F, kLaunchBits, c->Q0.as<uint2>(), nullptr, (uint32_t)med_ub);
+    }));
+    sv::TileArgs ta;
+    memset(&ta, 0, sizeof ta);
+    ta.G0 = F; ta.t0 = 0; ta.L = L; ta.l = l;
+    ta.pat = pat; ta.per = per; ta.patw = patw; ta.per_tile = (uint32_t)((1ull << L) % per);
+    ta.fixmask = pmask; ta.P = pr->P.as<uint32_t>(); ta.QP = c->Q0.as<uint2>();
+    ta.xon = use_xpat(B, L, l) ? 1u : 0u;
+    if (ta.xon) STCHK(get_xpattern(c, s, &ta.xpat));
+    ta.plan = plan; ta.b = R.b; ta.has_large = 0; ta.count_atomic = count_atomic ? 1 : 0;
+    ta.nwin = nwin;
+    uint32_t ntot = 0;
+    for (uint32_t w = 0; w < nwin; ++w) {
+      const uint64_t ls = (uint64_t)w * kLaunchBits, lb = std::min<uint64_t>(kLaunchBits, NB - ls);
+      sv::TileWin& W = ta.win[w];
+      W.G0 = F + ls;
+      W.lbits = (uint32_t)lb;
+      W.ntiles = (uint32_t)((lb + (1ull << L) - 1) >> L);
+      W.psq = (uint32_t)std::min<uint64_t>(isqrt_u64(2 * W.G0 + 1), 0xFFFFFFFFull);
+      W.per_G0 = (uint32_t)(W.G0 % per);
+      W.S = S + (ls >> 5);
+      W.counts = counts + (ls >> l);
+      W.QP = c->Q0.as<uint2>() + (size_t)w * med_ub;
+      ntot += W.ntiles;
+    }
+    ta.ntiles = ntot;
+    ta.lbits = ta.win[0].lbits; ta.psq = ta.win[0].psq; ta.per_G0 = ta.win[0].per_G0;
+    ta.S = S; ta.counts = counts;
+    STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(c, L, s, ta); }));
+    return SIEVE_OK;
+  }
   const uint32_t b = R.b;
   const uint32_t esz = b <= 16 ? 2 : 4;                        // bytes per bucket entry
   const uint64_t chunk_max = std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits);  // bits per bucket fill
@@ -715,7 +758,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       const uint64_t off_ub = tab_ub;  // grid over primes >= 17
       STCHK(launch(c, "k_offsets", s, [&] {
         sv::k_offsets<<<(uint32_t)((off_ub + 255) / 256), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits,
-                                                                       c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr);
+                                                                       c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr,
+                                                                       0);
       }));
     }
     const uint64_t psq = isqrt_u64(2 * G0 + 1);
@@ -981,13 +1025,13 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   const uint64_t tab_ub = pi_upper(B);
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
-  sv::k_plan<<<1, 1, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 17, 1ull << R.Wlog,
+  sv::k_plan<<<1, 64, 0, s>>>(c->own.P.as<uint32_t>(), c->own.cnt.as<uint32_t>(), B, 17, 1ull << R.Wlog,
                              1ull << R.Blog, med_lim, 1ull << (R.L - 3), (uint32_t)tab_ub, plan);
   STCHK(c->Q0.ensure(tab_ub * 8 + 64));
   STCHK(c->OFF.ensure(2 * tab_ub * 4 + 64));
   const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB);
   sv::k_offsets<<<(uint32_t)((tab_ub + 255) / 256), 256, 0, s>>>(c->own.P.as<uint32_t>(), plan, F, lbits,
-                                                                 c->Q0.as<uint2>(), c->OFF.as<uint32_t>());
+                                                                 c->Q0.as<uint2>(), c->OFF.as<uint32_t>(), 0);
   const uint32_t b = R.b, esz = b <= 16 ? 2 : 4;
   const uint64_t cbits = std::min<uint64_t>(std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits), lbits);
   const uint32_t nbins = (uint32_t)((cbits + (1ull << b) - 1) >> b);
