@@ -6,7 +6,10 @@ A step is one full sieve_init call on the workload: device prime generation up t
 B, first offsets, the large-prime bucket fill (when B reaches the bucket range),
 every LDS tile (pattern, medium primes, bucket drain, write-out with popcounts).
 Inputs are interval parameters; outputs land in HBM.  The line printed is one
-JSON object; see the DESIGN notes for the meaning of the roofline and baseline.
+JSON object.  Its roofline entry rates the tile kernel by algorithmic marks (every
+odd multiple of every prime 17 <= p <= B in the interval, at or above p^2) per
+second against one 32-bit LDS access per bank per clock on every CU; its
+cpu_baseline entry times the plain CPU oracle on the same interval.
 """
 import argparse
 import hashlib
@@ -19,7 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X figures used for the roofline ("Roofline").
+# MI355X figures used for the roofline.
 CUS, CLOCK_HZ = 256, 2.4e9
 LDS_PEAK_OPS = CUS * CLOCK_HZ * 32          # one 32-bit LDS access per bank per clock, 32 banks
 HBM_PEAK = 8.0e12                           # bytes/s
@@ -105,8 +108,7 @@ def run_plain(name, steps, warmup, check=True):
     for _ in range(warmup):
         api.sieve_init(l, f, n, B, S, c)
     torch.cuda.synchronize()
-    ctx.kernel_times()                     # drop anything recorded so far
-    ctx.set_timing(True)
+    # the timed steps: one event pair per step and nothing else on the stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -116,13 +118,25 @@ def run_plain(name, steps, warmup, check=True):
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    # the same steps again with an event pair around every kernel launch (on the
+    # stream it is launched on), for the per-kernel durations and the roofline
+    ctx.kernel_times()                     # drop anything recorded so far
+    ctx.set_timing(True)
+    ek = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ek:
+        a.record(stream)
+        api.sieve_init(l, f, n, B, S, c)
+        b.record(stream)
+    torch.cuda.synchronize()
     kt = ctx.kernel_times()
     ctx.set_timing(False)
-    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    step_ms_kev = sum(a.elapsed_time(b) for a, b in ek) / steps
     step_ms = sum(lat) / len(lat)
     numbers = v - u + 1
     out = {"name": name, "l": l, "f": f, "n": n, "B": B, "u": u, "v": v,
            "ms_per_step": step_ms, "wall_ms_per_step": 1e3 * wall / steps,
+           "ms_per_step_with_kernel_events": step_ms_kev,
            "numbers_per_s": numbers / (step_ms * 1e-3),
            "p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
            "kernels": {k: {"total_ms": ms / steps, "launches_per_step": nl / steps} for k, (ms, nl) in kt.items()}}
@@ -257,8 +271,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design of a sharded run is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(a sharded run would split the interval into contiguous segment ranges, one per GPU); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
@@ -291,6 +306,7 @@ def main():
                    % (args.workload, main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"], u, v),
                    "mode": "plain (one sieve_init per step, prime generation included)"},
         "p50_ms": main_rec["p50_ms"], "p99_ms": main_rec["p99_ms"],
+        "ms_per_step_with_kernel_events": main_rec["ms_per_step_with_kernel_events"],
         "bit_exact": main_rec.get("bit_exact"),
         "roofline": roof,
         "kernels_ms_per_step": {k: round(x["total_ms"], 4) for k, x in main_rec["kernels"].items()},
