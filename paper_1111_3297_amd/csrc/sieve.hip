@@ -451,25 +451,29 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
   uint32_t* P = pr->P.as<uint32_t>();
   uint32_t* cnt = pr->cnt.as<uint32_t>();
   if (B < 65536) {
-    STCHK(launch(c, "k_base_primes", s, [&] { sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)B, P, cnt); }));
+    STCHK(launch(c, "k_base_primes", s, [&] {
+      sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)B, P, cnt, nullptr, nullptr, 0, 17, 0, 0, 0, 0);
+    }));
   } else {
     // base primes up to isqrt(B) < 2^16, then one sieve of the odd numbers 1..B
     const uint64_t rb = isqrt_u64(B);
     STCHK(c->gen_blk.ensure(pi_upper(65536) * 4 + 64));
     uint32_t* base = c->gen_blk.as<uint32_t>();
     uint32_t* base_cnt = base + pi_upper(65536);
-    STCHK(launch(c, "k_base_primes", s, [&] { sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)rb, base, base_cnt); }));
     const uint32_t nbase_ub = (uint32_t)pi_upper(65536);
     STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
     sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
-    STCHK(launch(c, "k_plan", s, [&] {
-      sv::k_plan<<<1, 64, 0, s>>>(base, base_cnt, rb, use_xpat(rb, kGenTile, 15) ? 53 : 17, 1ull << 9, 1ull << 16,
-                                 1ull << 17, 1ull << (kGenTile - 3), nbase_ub, gplan);
+    STCHK(c->Q0.ensure(pi_upper(65536) * 8));
+    // base primes, the generator's plan and its launch offsets (from 0) in one kernel
+    STCHK(launch(c, "k_base_primes", s, [&] {
+      sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)rb, base, base_cnt, gplan, c->Q0.as<uint2>(), nbase_ub,
+                                           use_xpat(rb, kGenTile, 15) ? 53 : 17, 1u << 9, 1u << 16, 1u << 17,
+                                           1u << (kGenTile - 3));
     }));
     // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
     // 2^15-bit count segments (the extra bits are masked off by the compaction)
     const uint64_t kmax = (B - 1) / 2;
-    const uint32_t gl = 15;
+    constexpr uint32_t gl = 15;
     const uint64_t gbits = ((kmax + 1 + (1ull << gl) - 1) >> gl) << gl;
     const uint32_t L = kGenTile;
     const uint32_t ntiles = (uint32_t)((gbits + (1ull << L) - 1) >> L);
@@ -478,12 +482,7 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     const uint32_t ncnt = (uint32_t)(gbits >> gl);
     STCHK(c->gen_S.ensure(((size_t)nwords + nblk + ncnt + 64) * 4));
     uint32_t* gS = c->gen_S.as<uint32_t>();
-    uint32_t* gblk = gS + nwords;
-    uint32_t* gcounts = gblk + nblk + 32;
-    STCHK(c->Q0.ensure(pi_upper(65536) * 8));
-    STCHK(launch(c, "k_offsets", s, [&] {
-      sv::k_offsets<<<(nbase_ub + 255) / 256, 256, 0, s>>>(base, gplan, 0, gbits, c->Q0.as<uint2>(), nullptr, 0);
-    }));
+    uint32_t* gcounts = gS + nwords + 32;
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, rb, s, &pat, &per, &patw, &pmask));
     sv::TileArgs ta;
@@ -496,13 +495,15 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     ta.plan = gplan; ta.psq = 1; ta.has_large = 0; ta.b = 16;
     ta.S = gS; ta.counts = gcounts; ta.count_atomic = 0;
     STCHK(launch(c, "k_tile[gen]", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
-    STCHK(launch(c, "k_compact_count", s, [&] {
-      sv::k_compact_count<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk);
-    }));
+    // blocks of the compaction = count segments of the tile kernel (1024 words each)
+    static_assert(gl == 15, "compaction blocks are 2^15-bit count segments");
     STCHK(ensure_err(c, s));
-    STCHK(launch(c, "k_scan_small", s, [&] { sv::k_scan_small<<<1, 1024, 0, s>>>(gblk, nblk, cnt, (uint32_t)cap); }));
+    STCHK(launch(c, "k_scan_small", s, [&] {
+      sv::k_scan_small<<<1, 1024, 0, s>>>(gcounts, ncnt, cnt, (uint32_t)cap, gS, (uint32_t)kmax);
+    }));
     STCHK(launch(c, "k_compact_write", s, [&] {
-      sv::k_compact_write<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gblk, P, (uint32_t)cap, c->err.as<uint32_t>());
+      sv::k_compact_write<<<nblk, 1024, 0, s>>>(gS, nwords, (uint32_t)kmax, gcounts, P, (uint32_t)cap,
+                                                c->err.as<uint32_t>());
     }));
   }
   pr->B = B;
