@@ -103,6 +103,18 @@ def test_multi_chunk_and_bucket_path():
                tune={"tile_log2": 17, "medium_log2": 14, "bins_log2": 8, "bin_log2": 17, "groups": 80})
 
 
+@pytest.mark.parametrize("case", [
+    # 2^20-bit tiles over short segments: one word per lane at write-out (l = 12, no
+    # 17..47 masks) and four words per lane with the masks (l = 13)
+    (12, (10**9) >> 13, 512, 40000), (13, (10**9) >> 14, 256, 40000),
+    # the 17..47 masks need every prime up to 47
+    (20, 0, 2, 46), (20, 0, 2, 47), (20, 1, 2, 53), (20, (10**10) >> 21, 3, 47),
+])
+def test_write_out_paths_on_2p20_tiles(case):
+    l, f, n, B = case
+    check_case(l, f, n, B, tune={"tile_log2": 20})
+
+
 def test_carried_rows_across_tiles():
     # more tiles than workgroups, so each workgroup carries the next-hit offsets of
     # the largest medium primes from tile to tile; primes above sqrt(u) start at p^2
