@@ -34,7 +34,7 @@ thread_local int g_last_hip = 0;
   } while (0)
 
 constexpr uint64_t kLaunchBits = sv::kWinBits;  // offsets of one launch window fit 32 bits
-constexpr uint32_t kGenTile = 20;             // tile of the prime generator
+constexpr uint32_t kGenTile = 20;             // largest tile of the prime generator
 constexpr uint32_t kBatchRun = 4;             // consecutive tiles per batch work item
 constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or more use two bin ranges by default
 constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
@@ -460,6 +460,15 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     STCHK(c->gen_blk.ensure(pi_upper(65536) * 4 + 64));
     uint32_t* base = c->gen_blk.as<uint32_t>();
     uint32_t* base_cnt = base + pi_upper(65536);
+    // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
+    // 2^15-bit count segments (the extra bits are masked off by the compaction);
+    // tiles of 2^20 bits when there are a few hundred of them, else smaller tiles
+    // so that a short table still spreads over many compute units
+    const uint64_t kmax = (B - 1) / 2;
+    constexpr uint32_t gl = 15;
+    const uint64_t gbits = ((kmax + 1 + (1ull << gl) - 1) >> gl) << gl;
+    uint32_t L = gl;
+    while (L < kGenTile && (gbits >> (L + 9)) > 0) ++L;           // at least 256 tiles when possible
     const uint32_t nbase_ub = (uint32_t)pi_upper(65536);
     STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
     sv::Plan* gplan = c->plan.as<sv::Plan>() + 1;
@@ -467,15 +476,9 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     // base primes, the generator's plan and its launch offsets (from 0) in one kernel
     STCHK(launch(c, "k_base_primes", s, [&] {
       sv::k_base_primes<<<1, 1024, 0, s>>>((uint32_t)rb, base, base_cnt, gplan, c->Q0.as<uint2>(), nbase_ub,
-                                           use_xpat(rb, kGenTile, 15) ? 53 : 17, 1u << 9, 1u << 16, 1u << 17,
-                                           1u << (kGenTile - 3));
+                                           use_xpat(rb, L, gl) ? 53 : 17, 1u << 9, 1u << std::max(9u, L - 7),
+                                           1u << 17, 1u << (L - 3));
     }));
-    // the generator table: bit k <-> 2k+1, k = 0..(B-1)/2, rounded up to whole
-    // 2^15-bit count segments (the extra bits are masked off by the compaction)
-    const uint64_t kmax = (B - 1) / 2;
-    constexpr uint32_t gl = 15;
-    const uint64_t gbits = ((kmax + 1 + (1ull << gl) - 1) >> gl) << gl;
-    const uint32_t L = kGenTile;
     const uint32_t ntiles = (uint32_t)((gbits + (1ull << L) - 1) >> L);
     const uint32_t nwords = (uint32_t)(gbits / 32);
     const uint32_t nblk = (nwords + 1023) / 1024;
