@@ -497,6 +497,8 @@ int build_primes(sieve_ctx* c, uint64_t B, sieve_primes* pr, hipStream_t s) {
     if (ta.xon) STCHK(get_xpattern(c, s, &ta.xpat));
     ta.plan = gplan; ta.psq = 1; ta.has_large = 0; ta.b = 16;
     ta.S = gS; ta.counts = gcounts; ta.count_atomic = 0;
+    ta.nwin = 1;
+    ta.win[0] = {ta.G0, ta.lbits, ntiles, ta.psq, ta.per_G0, ta.S, ta.counts, ta.QP};
     STCHK(launch(c, "k_tile[gen]", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
     // blocks of the compaction = count segments of the tile kernel (1024 words each)
     static_assert(gl == 15, "compaction blocks are 2^15-bit count segments");
@@ -782,6 +784,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     ta.bucket = large ? c->bucket.p : nullptr; ta.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
     ta.b = b; ta.nbins = ch.nbins; ta.cap = (uint32_t)cap; ta.has_large = large ? 1 : 0;
     ta.S = S + (ch.ls >> 5); ta.counts = counts + (ch.ls >> l); ta.count_atomic = count_atomic ? 1 : 0;
+    ta.nwin = 1;
+    ta.win[0] = {ta.G0, ta.lbits, ntiles, ta.psq, ta.per_G0, ta.S, ta.counts, ta.QP};
     if (esz == 2)
       STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
     else
