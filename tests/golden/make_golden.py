@@ -9,6 +9,8 @@ Workloads (interval parameters of Section 1.2.1):
   interval_1e12    : l=20, n=4096, f=floor((10^12 - 2^32)/2^21), B = isqrt(v)
   interval_1e12_b6 : the same interval with the literal bound B = 10^6 (partial sieve)
   interval_2p60    : l=20, n=4096, f=2^39-2048 (centred at 2^60), B = 2^30
+  interval_3win    : l=20, n=5120 from 512 segments below interval_1e12's start,
+                     B = isqrt(v): three launch windows of 2^31, 2^31 and 2^30 bits
   batch_1234       : the 256 interval requests of the seeded batch workload
                      (paper_1111_3297_amd/workloads.py), B = isqrt(v) each
 Run: python tests/golden/make_golden.py [name ...]
@@ -34,6 +36,7 @@ def workloads():
         "interval_1e12": (20, F_1E12, 4096, math.isqrt(v)),
         "interval_1e12_b6": (20, F_1E12, 4096, 10**6),
         "interval_2p60": (20, 2**39 - 2048, 4096, 2**30),
+        "interval_3win": (20, F_1E12 - 512, 5120, math.isqrt(O.interval(20, F_1E12 - 512, 5120)[1])),
     }
 
 

@@ -209,7 +209,7 @@ def _golden(name):
         return json.load(fh)
 
 
-@pytest.mark.parametrize("name", ["interval_1e12", "interval_1e12_b6", "interval_2p60"])
+@pytest.mark.parametrize("name", ["interval_1e12", "interval_1e12_b6", "interval_2p60", "interval_3win"])
 def test_full_size_against_oracle_golden(name):
     g = _golden(name)
     say("full size", name, g["l"], g["f"], g["n"], g["B"])
