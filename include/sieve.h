@@ -65,8 +65,9 @@ typedef enum {
  *   wave_log2   medium primes below 2^wave_log2 are sieved by a whole wavefront
  *               each, those below 2^wheel_log2 by eight lanes each (one per
  *               residue of the 3-5 wheel, Section 3.2.1), the rest by one lane
- *               each with every hit: the GPU form of the per-hit-count grouping
- *               of Section 3.2.2.  9 <= wave_log2 <= wheel_log2 <= medium_log2.
+ *               each (walking the wheel when a prime has eight or more hits per
+ *               tile): the GPU form of the per-hit-count grouping of Section
+ *               3.2.2.  9 <= wave_log2 <= wheel_log2 <= medium_log2.
  *               Defaults 9 and min(tile_log2-7, medium_log2) (at least 9).
  *   bins_log2   log2 of the number of large-prime buckets per chunk, 8..15.
  *   groups      workgroups of the bucket-fill kernels, 64..2048; default 1024.
@@ -147,8 +148,8 @@ int sieve_ctx_sieve_with(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uin
 /* --- batched persistent launch ---
  * Sieves every request of reqs[0..nreq) (all with segment size 2^l) against the
  * one shared table pr: one offset kernel, one bucket fill and one persistent tile
- * kernel for the whole batch, whose workgroups take (request, tile) work items
- * from a device queue, longest first.  Each request's table and counts are the
+ * kernel for the whole batch, whose workgroups take (request, run of up to four
+ * consecutive tiles) work items from a device queue, longest first.  Each request's table and counts are the
  * same as sieve_init would give for it alone. */
 int sieve_batch(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
                 size_t nreq, const sieve_tune *tune, void *stream);
