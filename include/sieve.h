@@ -70,7 +70,7 @@ typedef enum {
  *               3.2.2.  9 <= wave_log2 <= wheel_log2 <= medium_log2.
  *               Defaults 9 and min(tile_log2-7, medium_log2) (at least 9).
  *   bins_log2   log2 of the number of large-prime buckets per chunk, 8..15.
- *   groups      workgroups of the bucket-fill kernels, 64..2048; default 1024.
+ *   groups      workgroups of the bucket-fill kernels, 64..4096; default 2048.
  *               Each takes a contiguous slice of the large primes of equal
  *               estimated work.  With ranges given, a chunk's workgroups are split
  *               over its ranges (groups rounded down to a multiple of ranges);

@@ -110,8 +110,8 @@ int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
   if (r->binslog < 8 || r->binslog > 15) return SIEVE_E_ARG;
   r->R = t->ranges;                              // 0: chosen per chunk
   if (r->R != 0 && r->R != 1 && r->R != 2 && r->R != 4 && r->R != 8) return SIEVE_E_ARG;
-  r->groups = t->groups ? t->groups : 1024;
-  if (r->groups < 64 || r->groups > 2048) return SIEVE_E_ARG;
+  r->groups = t->groups ? t->groups : 2048;
+  if (r->groups < 64 || r->groups > 4096) return SIEVE_E_ARG;
   if (r->R) r->groups -= r->groups % r->R;
   return SIEVE_OK;
 }
@@ -334,7 +334,7 @@ uint64_t set_stages(std::vector<sv::BucketJob>& jobs, size_t j0, size_t j1, uint
   uint64_t pad = 0;
   for (size_t k = j0; k < j1; ++k) {
     jobs[k].sbl = stage_log2(lds, jobs[k].rbins, esz, jobs[k].sbl);
-    pad += (uint64_t)jobs[k].GR * jobs[k].rbins * (16 / esz - 1);
+    pad += (uint64_t)jobs[k].GR * jobs[k].rbins * (sv::kRegionBytes / esz - 1);
   }
   if (lds_out) *lds_out = lds;
   return pad;
@@ -1054,7 +1054,7 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   STCHK(c->bstart.ensure((2 * nbins + 2) * 4));
   uint32_t lds = 0, pad_bin = 0;
   const uint64_t pad = set_stages(c->h_jobs, 0, c->h_jobs.size(), esz, &lds);
-  for (auto& J : c->h_jobs) pad_bin = std::max(pad_bin, J.GR * (16 / esz - 1));
+  for (auto& J : c->h_jobs) pad_bin = std::max(pad_bin, J.GR * (sv::kRegionBytes / esz - 1));
   const double rs = recip_sum_upper((double)med_lim, (double)B);
   const uint64_t cap = (uint64_t)(1.02 * rs * (double)cbits) + tab_ub + 4096 + pad;
   if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
@@ -1177,7 +1177,7 @@ uint64_t batch_bytes(const std::vector<Window>& W, const Resolved& R, uint32_t l
     if (w.B >= med_lim) {
       const uint64_t nb = (w.lbits + (1ull << R.b) - 1) >> R.b;
       // at most 256 workgroups per request, each with a group-rounded region per bin
-      cap += window_cap(w, med_lim) + 256 * nb * (16 / esz - 1);
+      cap += window_cap(w, med_lim) + 256 * nb * (sv::kRegionBytes / esz - 1);
       bins += nb;
       hg += nb * 256;
     }
