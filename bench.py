@@ -43,6 +43,26 @@ def marks_algorithmic(primes, u, v):
     return float(cnt.sum())
 
 
+def marks_executed(primes, u, v, tile_log2=20, first_med=53):
+    """LDS atomics the tile kernel executes at its default classes for 2^tile_log2-bit
+    tiles: primes below first_med come from the write-out masks, primes from first_med
+    to 2^(tile_log2-3) mark only the multiples m*p whose cofactor m is prime to 15 (the
+    3-5 wheel), larger primes every odd multiple; all from max(u, p^2) to v."""
+    import numpy as np
+    assert v < (1 << 62)
+    p = primes[primes >= first_med].astype(np.int64)
+    m0 = np.maximum(-(-int(u) // p), p)                   # ceil(u / p), at least p
+    m1 = int(v) // p
+    wheel = p < (1 << (tile_log2 - 3))
+    res = np.array([sum(1 for s in (1, 7, 11, 13, 17, 19, 23, 29) if s <= r) for r in range(30)], dtype=np.int64)
+    coprime30 = lambda x: 8 * (x // 30) + res[x % 30]     # k in [1, x] with gcd(k, 30) = 1
+    w = np.where(m1 >= m0, coprime30(m1) - coprime30(m0 - 1), 0)
+    o0 = m0 + (1 - m0 % 2)
+    o1 = m1 - (1 - m1 % 2)
+    a = np.where(o1 >= o0, (o1 - o0) // 2 + 1, 0)
+    return float(np.where(wheel, w, a).sum())
+
+
 def large_hits(primes, u, v, med_lim):
     import numpy as np
     p = primes[primes >= med_lim].astype(np.float64)
@@ -243,6 +263,39 @@ def run_serving_bench(seconds, tune):
             "plain_fcfs": {k: st0[k] for k in keep}}
 
 
+def unit_rates():
+    """Measured unit rates the roofline figures are set against: the library's LDS-atomic and
+    VALU microbenchmarks (sieve_microbench, median of three) and its plain HBM copy of 1 GiB."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api, _lib
+    rates = {}
+    for kind, rounds in (("lds_or_random", 2048), ("lds_or_spread", 2048), ("valu_int32", 16384)):
+        api.microbench(kind, 64)                                  # warm-up
+        rates[kind + "_per_s"] = float(np.median([api.microbench(kind, rounds) for _ in range(3)]))
+    nb = 1 << 30
+    a = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    copy = lambda: _lib.check(_lib.load().sieve_copy_calibration(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                                                  nb, ctypes.c_void_p(st.cuda_stream)), "sieve_copy_calibration")
+    copy()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(5):
+        copy()
+    e1.record(st)
+    e1.synchronize()
+    rates["hbm_copy_bytes_per_s"] = 5 * 2.0 * nb / (e0.elapsed_time(e1) * 1e-3)   # bytes read + written
+    del a, b
+    clk_cu = 2.4e9 * 256
+    rates["per_clock_per_cu"] = {"lds_or_random": rates["lds_or_random_per_s"] / clk_cu,
+                                 "lds_or_spread": rates["lds_or_spread_per_s"] / clk_cu,
+                                 "valu_int32": rates["valu_int32_per_s"] / clk_cu}
+    return rates
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +306,8 @@ def main():
     ap.add_argument("--also", default="interval_2p60", help="comma list of extra plain workloads to report")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches (0: skip the batch bench)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of the request stream to replay (0: skip)")
+    ap.add_argument("--no-unit-rates", action="store_true", help="skip the LDS / VALU / copy microbenchmarks")
+    ap.add_argument("--unit-rates-only", action="store_true", help="only run the microbenchmarks and print their rates")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run the library's plain copy kernel over this many bytes, 5 times (counter calibration)")
     args = ap.parse_args()
@@ -269,6 +324,9 @@ def main():
                        "sieve_copy_calibration")
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}))
+        return
+    if args.unit_rates_only:
+        print(json.dumps({"unit_rates": unit_rates()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -290,6 +348,14 @@ def main():
             "unit": "Gmarks/s", "frac": achieved / LDS_PEAK_OPS, "traffic": traffic,
             "per_launch": {"marks": marks_per_launch, "avg_ms": per_launch_ms,
                            "launches_per_step": kt["launches_per_step"]}}
+    rates = None if args.no_unit_rates else unit_rates()
+    if rates is not None and main_rec["l"] == 20:
+        # the LDS atomics actually issued (wheel and masks leave out about half the
+        # algorithmic marks) against the measured random-address ds_or_b32 rate
+        ex = marks_executed(primes, u, v) / kt["launches_per_step"]
+        roof["vs_measured_lds"] = {"executed_marks": ex, "executed_per_s": ex / (per_launch_ms * 1e-3),
+                                   "lds_or_random_per_s": rates["lds_or_random_per_s"],
+                                   "frac": ex / (per_launch_ms * 1e-3) / rates["lds_or_random_per_s"]}
     also = {}
     for name in [x for x in args.also.split(",") if x and x != "none"]:
         rec = run_plain(name, max(3, args.steps // 4), 2)
@@ -322,6 +388,8 @@ def main():
         tune = out["batch"]["tune"]
     if args.serve_seconds > 0:
         out["serving"] = run_serving_bench(args.serve_seconds, tune)
+    if rates is not None:
+        out["unit_rates"] = rates
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"])
     print(json.dumps(out), flush=True)

@@ -182,6 +182,22 @@ sieve_ctx *sieve_default_ctx(void);
 /* Plain device copy of nbytes (multiple of 16) used to calibrate traffic counters. */
 int sieve_copy_calibration(const void *src_dev, void *dst_dev, uint64_t nbytes, void *stream);
 
+/* --- unit microbenchmarks ---
+ * The measured rates the roofline figures are set against.  Runs one kernel of the
+ * given kind on stream in the calling thread's default context, SYNCHRONISES, and
+ * stores in *ops_per_s the operations per second of the whole device, timed with a
+ * HIP event pair around the launch.  rounds (1 .. 2^20) sets the length:
+ *   SIEVE_MB_LDS_OR_RANDOM  ds_or_b32 of 1024-lane workgroups (one per CU at a time)
+ *                           into random words of a 2^20-bit LDS array, the access
+ *                           pattern of the tile kernel's marks; 16 per lane per round
+ *   SIEVE_MB_LDS_OR_SPREAD  the same with the lanes of a half wave on 32 different
+ *                           banks (no bank conflicts)
+ *   SIEVE_MB_VALU           32-bit integer adds and xors, eight independent chains per
+ *                           lane, 16 per lane per round, eight waves per SIMD
+ * Operations are counted per lane. */
+enum { SIEVE_MB_LDS_OR_RANDOM = 0, SIEVE_MB_LDS_OR_SPREAD = 1, SIEVE_MB_VALU = 2 };
+int sieve_microbench(uint32_t kind, uint32_t rounds, double *ops_per_s, void *stream);
+
 /* --- inspection (tests) ---
  * Runs the offset and bucket-fill kernels for the first chunk of (l, f, n, B) and
  * copies the bucket layout to host memory: bin_start (nbins+1 entries) and the

@@ -19,8 +19,10 @@ EXPORTS = [
     "sieve_primes_create", "sieve_primes_destroy", "sieve_primes_info", "sieve_primes_copy",
     "sieve_ctx_sieve_with", "sieve_batch", "sieve_batch_scratch_bytes", "sieve_required_bound",
     "sieve_strerror", "sieve_last_hip_error", "sieve_check_device_errors", "sieve_ctx_set_timing",
-    "sieve_ctx_kernel_times", "sieve_default_ctx", "sieve_copy_calibration", "sieve_debug_buckets",
+    "sieve_ctx_kernel_times", "sieve_default_ctx", "sieve_copy_calibration", "sieve_microbench",
+    "sieve_debug_buckets",
 ]
+MB_LDS_OR_RANDOM, MB_LDS_OR_SPREAD, MB_VALU = 0, 1, 2
 
 
 class SieveError(RuntimeError):
@@ -80,6 +82,7 @@ def load():
                                          ctypes.POINTER(u32)]),
         "sieve_default_ctx": (vp, []),
         "sieve_copy_calibration": (i32, [vp, vp, u64, vp]),
+        "sieve_microbench": (i32, [u32, u32, ctypes.POINTER(ctypes.c_double), vp]),
         "sieve_debug_buckets": (i32, [u32, u64, u64, u64, ctypes.POINTER(Tune), vp, u32, vp, u64,
                                       ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64),
                                       ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32)]),

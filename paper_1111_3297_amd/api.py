@@ -182,3 +182,15 @@ def debug_buckets(l, f, n, B, tune=None, entry_cap=1 << 26):
     return {"bin_start": bins[:nbins.value + 1].copy(), "entries": ent[:min(ne.value, entry_cap)].copy(),
             "bin_log2": blog.value, "chunk_bits": cb.value, "nlarge": nl.value, "nentries": ne.value,
             "pad_per_bin": pad.value}
+
+
+MICROBENCH = {"lds_or_random": L.MB_LDS_OR_RANDOM, "lds_or_spread": L.MB_LDS_OR_SPREAD, "valu_int32": L.MB_VALU}
+
+
+def microbench(kind, rounds=2048, stream=None):
+    """Operations per second of one unit microbenchmark (include/sieve.h: sieve_microbench);
+    kind is a key of MICROBENCH.  Synchronises."""
+    rate = ctypes.c_double()
+    L.check(L.load().sieve_microbench(MICROBENCH[kind], rounds, ctypes.byref(rate), _stream(stream)),
+            "sieve_microbench")
+    return rate.value

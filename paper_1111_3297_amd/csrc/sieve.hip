@@ -149,7 +149,7 @@ struct sieve_ctx {
   bool has_last = false;
   hipEvent_t done = nullptr;
   // scratch
-  DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk;
+  DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk, mb_sink;
   // batch scratch and the host copies of its tables
   DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, cjobs, cblk2job, thr;
   std::vector<sv::BatchReq> h_req;
@@ -177,7 +177,7 @@ struct sieve_ctx {
 
 sieve_ctx::~sieve_ctx() {
   if (has_last) (void)hipStreamSynchronize(last_stream);
-  DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk,
+  DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
                     &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
                     &own.P, &own.cnt};
   for (DevBuf* b : bufs) b->release();
@@ -1011,6 +1011,43 @@ int sieve_copy_calibration(const void* src_dev, void* dst_dev, uint64_t nbytes, 
   sv::k_copy16<<<2048, 256, 0, s>>>((const uint4*)src_dev, (uint4*)dst_dev, nbytes / 16);
   HIPCHK(hipGetLastError());
   return SIEVE_OK;
+}
+
+int sieve_microbench(uint32_t kind, uint32_t rounds, double* ops_per_s, void* stream) {
+  if (!ops_per_s || kind > SIEVE_MB_VALU || rounds == 0 || rounds > (1u << 20)) return SIEVE_E_ARG;
+  sieve_ctx* c = sieve_default_ctx();
+  if (!c) return SIEVE_E_HIP;
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(c, s));
+  STCHK(c->mb_sink.ensure(256));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SIEVE_E_HIP; }
+  double ops = 0;
+  hipError_t e = hipEventRecord(e0, s);
+  if (e == hipSuccess) {
+    if (kind == SIEVE_MB_VALU) {
+      const uint32_t grid = 8 * c->ncu;                        // eight waves per SIMD
+      sv::k_mb_valu<<<grid, 256, 0, s>>>(rounds, 12345u, c->mb_sink.as<uint32_t>());
+      ops = (double)grid * 256.0 * rounds * sv::kMbChains * 2.0;
+    } else {
+      const uint32_t grid = 4 * c->ncu;                        // four rounds of one workgroup per CU
+      sv::k_mb_lds<<<grid, 1024, 0, s>>>(kind == SIEVE_MB_LDS_OR_SPREAD ? 1u : 0u, rounds, 12345u,
+                                         c->mb_sink.as<uint32_t>());
+      ops = (double)grid * 1024.0 * rounds * sv::kMbAddrs;
+    }
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) { g_last_hip = (int)e; return SIEVE_E_HIP; }
+  *ops_per_s = ms > 0 ? ops / (1e-3 * ms) : 0.0;
+  return end(c, s);
 }
 
 int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune* tune,

@@ -38,6 +38,11 @@ def test_argument_errors_without_gpu():
     assert lib.sieve_init(10, 0, 0, 3, dummy, dummy, None) == E["SIEVE_E_ARG"]
     assert lib.sieve_init(10, 0, 1, 2, dummy, dummy, None) == E["SIEVE_E_BOUND"]
     assert lib.sieve_init(10, 0, 1, 1 << 32, dummy, dummy, None) == E["SIEVE_E_BOUND"]
+    rate = ctypes.c_double(0)
+    assert lib.sieve_microbench(3, 10, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_microbench(0, 0, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_microbench(0, (1 << 20) + 1, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_microbench(2, 10, None, None) == E["SIEVE_E_ARG"]
     assert lib.sieve_init(20, 1 << 43, 1, 3, dummy, dummy, None) == E["SIEVE_E_RANGE"]
     assert lib.sieve_init(10, 0, 1, 3, None, dummy, None) == E["SIEVE_E_ARG"]
     B = ctypes.c_uint64()
