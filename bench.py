@@ -264,14 +264,15 @@ def run_serving_bench(seconds, tune):
 
 
 def unit_rates():
-    """Measured unit rates the roofline figures are set against: the library's LDS-atomic and
-    VALU microbenchmarks (sieve_microbench, median of three) and its plain HBM copy of 1 GiB."""
+    """Measured unit rates the roofline figures are set against: the library's LDS-atomic, VALU
+    and 64-bit remainder microbenchmarks (sieve_microbench, median of three) and its plain HBM
+    copy of 1 GiB."""
     import ctypes
     import numpy as np
     import torch
     from paper_1111_3297_amd import api, _lib
     rates = {}
-    for kind, rounds in (("lds_or_random", 2048), ("lds_or_spread", 2048), ("valu_int32", 16384)):
+    for kind, rounds in (("lds_or_random", 2048), ("lds_or_spread", 2048), ("valu_int32", 16384), ("mod64", 1024)):
         api.microbench(kind, 64)                                  # warm-up
         rates[kind + "_per_s"] = float(np.median([api.microbench(kind, rounds) for _ in range(3)]))
     nb = 1 << 30

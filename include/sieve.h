@@ -194,8 +194,11 @@ int sieve_copy_calibration(const void *src_dev, void *dst_dev, uint64_t nbytes, 
  *                           banks (no bank conflicts)
  *   SIEVE_MB_VALU           32-bit integer adds and xors, eight independent chains per
  *                           lane, 16 per lane per round, eight waves per SIMD
+ *   SIEVE_MB_MOD64          the 64-bit by 32-bit remainder of the offset computation
+ *                           (Lemma 1's r), four independent chains per lane, 4 per lane
+ *                           per round, eight waves per SIMD
  * Operations are counted per lane. */
-enum { SIEVE_MB_LDS_OR_RANDOM = 0, SIEVE_MB_LDS_OR_SPREAD = 1, SIEVE_MB_VALU = 2 };
+enum { SIEVE_MB_LDS_OR_RANDOM = 0, SIEVE_MB_LDS_OR_SPREAD = 1, SIEVE_MB_VALU = 2, SIEVE_MB_MOD64 = 3 };
 int sieve_microbench(uint32_t kind, uint32_t rounds, double *ops_per_s, void *stream);
 
 /* --- inspection (tests) ---

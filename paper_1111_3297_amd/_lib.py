@@ -22,7 +22,7 @@ EXPORTS = [
     "sieve_ctx_kernel_times", "sieve_default_ctx", "sieve_copy_calibration", "sieve_microbench",
     "sieve_debug_buckets",
 ]
-MB_LDS_OR_RANDOM, MB_LDS_OR_SPREAD, MB_VALU = 0, 1, 2
+MB_LDS_OR_RANDOM, MB_LDS_OR_SPREAD, MB_VALU, MB_MOD64 = 0, 1, 2, 3
 
 
 class SieveError(RuntimeError):

@@ -184,7 +184,8 @@ def debug_buckets(l, f, n, B, tune=None, entry_cap=1 << 26):
             "pad_per_bin": pad.value}
 
 
-MICROBENCH = {"lds_or_random": L.MB_LDS_OR_RANDOM, "lds_or_spread": L.MB_LDS_OR_SPREAD, "valu_int32": L.MB_VALU}
+MICROBENCH = {"lds_or_random": L.MB_LDS_OR_RANDOM, "lds_or_spread": L.MB_LDS_OR_SPREAD, "valu_int32": L.MB_VALU,
+              "mod64": L.MB_MOD64}
 
 
 def microbench(kind, rounds=2048, stream=None):

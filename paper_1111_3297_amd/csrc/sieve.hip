@@ -1014,7 +1014,7 @@ int sieve_copy_calibration(const void* src_dev, void* dst_dev, uint64_t nbytes, 
 }
 
 int sieve_microbench(uint32_t kind, uint32_t rounds, double* ops_per_s, void* stream) {
-  if (!ops_per_s || kind > SIEVE_MB_VALU || rounds == 0 || rounds > (1u << 20)) return SIEVE_E_ARG;
+  if (!ops_per_s || kind > SIEVE_MB_MOD64 || rounds == 0 || rounds > (1u << 20)) return SIEVE_E_ARG;
   sieve_ctx* c = sieve_default_ctx();
   if (!c) return SIEVE_E_HIP;
   std::lock_guard<std::mutex> g(c->mu);
@@ -1027,7 +1027,11 @@ int sieve_microbench(uint32_t kind, uint32_t rounds, double* ops_per_s, void* st
   double ops = 0;
   hipError_t e = hipEventRecord(e0, s);
   if (e == hipSuccess) {
-    if (kind == SIEVE_MB_VALU) {
+    if (kind == SIEVE_MB_MOD64) {
+      const uint32_t grid = 8 * c->ncu;
+      sv::k_mb_mod64<<<grid, 256, 0, s>>>(rounds, 12345u, c->mb_sink.as<uint32_t>());
+      ops = (double)grid * 256.0 * rounds * sv::kMbModChains;
+    } else if (kind == SIEVE_MB_VALU) {
       const uint32_t grid = 8 * c->ncu;                        // eight waves per SIMD
       sv::k_mb_valu<<<grid, 256, 0, s>>>(rounds, 12345u, c->mb_sink.as<uint32_t>());
       ops = (double)grid * 256.0 * rounds * sv::kMbChains * 2.0;

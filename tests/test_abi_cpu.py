@@ -39,7 +39,7 @@ def test_argument_errors_without_gpu():
     assert lib.sieve_init(10, 0, 1, 2, dummy, dummy, None) == E["SIEVE_E_BOUND"]
     assert lib.sieve_init(10, 0, 1, 1 << 32, dummy, dummy, None) == E["SIEVE_E_BOUND"]
     rate = ctypes.c_double(0)
-    assert lib.sieve_microbench(3, 10, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_microbench(4, 10, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
     assert lib.sieve_microbench(0, 0, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
     assert lib.sieve_microbench(0, (1 << 20) + 1, ctypes.byref(rate), None) == E["SIEVE_E_ARG"]
     assert lib.sieve_microbench(2, 10, None, None) == E["SIEVE_E_ARG"]

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 CLK_CU = 2.4e9 * 256      # clock x compute units of the device
 
 
-@pytest.mark.parametrize("kind", ["lds_or_random", "lds_or_spread", "valu_int32"])
+@pytest.mark.parametrize("kind", ["lds_or_random", "lds_or_spread", "valu_int32", "mod64"])
 def test_microbench_rates(kind):
     from paper_1111_3297_amd import api
     say("microbench %s" % kind)
