@@ -207,7 +207,7 @@ int sieve_microbench(uint32_t kind, uint32_t rounds, double *ops_per_s, void *st
  * in-bin offsets of every large-prime hit, widened to 32 bits (entries, up to cap).  A
  * bin's entries are its hits, each at least once, plus padding that repeats hits of
  * the bin: at most *pad_per_bin extra entries per bin (each workgroup's region of a
- * bin is rounded up to 16 bytes).  Returns the number of bins in *nbins, the bin width log2 in
+ * bin is rounded up to 64 bytes).  Returns the number of bins in *nbins, the bin width log2 in
  * *bin_log2, the number of bits covered in *chunk_bits and the number of large
  * primes in *nlarge.  Synchronises. */
 int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const sieve_tune *tune,
