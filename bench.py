@@ -77,10 +77,16 @@ def large_hits(primes, u, v, med_lim):
 
 
 def kernel_source_hash():
+    """Hash of the library's code with comments and whitespace removed, so that a
+    comment-only edit keeps the committed counter summaries valid."""
+    import re
     h = hashlib.sha256()
     for rel in ("paper_1111_3297_amd/csrc/kernels.inc", "paper_1111_3297_amd/csrc/sieve.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
