@@ -655,7 +655,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(counts, n, 0); }));
     }
     STCHK(launch(c, "k_offsets", s, [&] {
-      sv::k_offsets<<<dim3((uint32_t)((tab_ub + 255) / 256), nwin), 256, 0, s>>>(
+      sv::k_offsets<<<dim3((uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), nwin), 256, 0, s>>>(
           pr->P.as<uint32_t>(), plan, F, kLaunchBits, c->Q0.as<uint2>(), nullptr, (uint32_t)med_ub);
     }));
     sv::TileArgs ta;
@@ -763,7 +763,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       cur_ls = ch.ls;
       const uint64_t off_ub = tab_ub;  // grid over primes >= 17
       STCHK(launch(c, "k_offsets", s, [&] {
-        sv::k_offsets<<<(uint32_t)((off_ub + 255) / 256), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits,
+        sv::k_offsets<<<(uint32_t)((off_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits,
                                                                        c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr,
                                                                        0);
       }));
@@ -1079,7 +1079,7 @@ int sieve_debug_buckets(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const si
   STCHK(c->Q0.ensure(tab_ub * 8 + 64));
   STCHK(c->OFF.ensure(2 * tab_ub * 4 + 64));
   const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB);
-  sv::k_offsets<<<(uint32_t)((tab_ub + 255) / 256), 256, 0, s>>>(c->own.P.as<uint32_t>(), plan, F, lbits,
+  sv::k_offsets<<<(uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), 256, 0, s>>>(c->own.P.as<uint32_t>(), plan, F, lbits,
                                                                  c->Q0.as<uint2>(), c->OFF.as<uint32_t>(), 0);
   const uint32_t b = R.b, esz = b <= 16 ? 2 : 4;
   const uint64_t cbits = std::min<uint64_t>(std::min<uint64_t>((1ull << R.binslog) << b, kLaunchBits), lbits);
