@@ -122,6 +122,32 @@ def cpu_baseline(l, f, n, B, budget_s=12.0):
                       % (ns, n, numbers, dt)}
 
 
+def cpu_baseline_all_cores(l, f, n, B, per_proc_s=8.0):
+    """The same oracle in one process per host core (at most 16), each on its own contiguous
+    range of segments of the workload, timed from the first start to the last end."""
+    import subprocess
+    from oracle import oracle as O
+    O.build()
+    procs = max(1, min(16, os.cpu_count() or 1))
+    n0 = max(1, min(n, 8))
+    t = time.perf_counter()
+    O.count_total(l, f, n0, B)
+    per_seg = max(time.perf_counter() - t, 1e-6) / n0
+    each = max(1, min(n // procs, int(per_proc_s / per_seg)))
+    code = ("import sys; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "O.count_total(%d, int(sys.argv[1]), %d, %d)" % (ROOT, l, each, B))
+    t = time.perf_counter()
+    ps = [subprocess.Popen([sys.executable, "-c", code, str(f + k * each)]) for k in range(procs)]
+    rcs = [q.wait() for q in ps]
+    wall = time.perf_counter() - t
+    if any(rcs):
+        return None
+    numbers = procs * each * (1 << (l + 1))
+    return {"value": numbers / wall, "unit": "numbers/s", "cores": procs, "kind": "oracle",
+            "sample": "segments %d..%d of %d (%d numbers) of the same interval and bound, %d processes of %d "
+                      "segments, %.1f s" % (0, procs * each - 1, n, numbers, procs, each, wall)}
+
+
 def run_plain(name, steps, warmup, check=True):
     import numpy as np
     import torch
@@ -399,6 +425,8 @@ def main():
         out["unit_rates"] = rates
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"])
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(main_rec["l"], main_rec["f"], main_rec["n"],
+                                                               main_rec["B"])
     print(json.dumps(out), flush=True)
 
 
