@@ -1,0 +1,63 @@
+"""CPU checks of the benchmark's work accounting: the algorithmic and the executed
+mark counts behind the roofline figures, against brute force on small intervals."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _primes(n):
+    s = np.ones(n + 1, bool)
+    s[:2] = False
+    for i in range(2, int(n ** 0.5) + 1):
+        if s[i]:
+            s[i * i::i] = False
+    return np.nonzero(s)[0]
+
+
+def _brute(P, u, v, tile_log2):
+    alg = exe = 0
+    for p in P:
+        if p < 17:
+            continue
+        for N in range(max(u, p * p), v + 1):
+            if N % p or N % 2 == 0:
+                continue
+            alg += 1
+            m = N // p
+            if p >= 53 and (p >= (1 << (tile_log2 - 3)) or (m % 3 and m % 5)):
+                exe += 1
+    return alg, exe
+
+
+def test_mark_counts_match_brute_force():
+    P = _primes(3000)
+    P = P[P >= 3]
+    for (u, v, L) in [(1, 120000, 15), (1000001, 1130000, 16), (12345679, 12405679, 17), (3, 9000, 13)]:
+        alg, exe = _brute(P, u, v, L)
+        assert bench.marks_algorithmic(P, u, v) == alg, (u, v)
+        assert bench.marks_executed(P, u, v, tile_log2=L) == exe, (u, v, L)
+
+
+def test_kernel_hash_ignores_comments(tmp_path):
+    src = os.path.join(ROOT, "paper_1111_3297_amd", "csrc")
+    d = tmp_path / "paper_1111_3297_amd" / "csrc"
+    d.mkdir(parents=True)
+    for name in ("kernels.inc", "sieve.hip"):
+        text = open(os.path.join(src, name)).read()
+        (d / name).write_text("// an added comment\n" + text.replace("\n", "\n  ", 3) + "\n/* trailing */\n")
+    h0 = bench.kernel_source_hash()
+    old = bench.ROOT
+    try:
+        bench.ROOT = str(tmp_path)
+        h1 = bench.kernel_source_hash()
+        (d / "kernels.inc").write_text((d / "kernels.inc").read_text() + "\nint changed;\n")
+        h2 = bench.kernel_source_hash()
+    finally:
+        bench.ROOT = old
+    assert h0 == h1 and h1 != h2
