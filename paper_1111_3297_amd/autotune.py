@@ -49,6 +49,13 @@ def candidates(l, bmax):
     return out
 
 
+def bucket_candidates():
+    """Bucket-layout variants tried around the best tile setting: the number of
+    bucket-fill workgroups (a batch shares them out over its requests by estimated
+    work; the library's default is 2048)."""
+    return [{"groups": 1024}, {"groups": 4096}]
+
+
 def _load(path):
     data = {}
     for p in (BUILTIN, path):
@@ -108,6 +115,16 @@ def tune_batch(primes, l, outs, ctx=None, cache_path=None, force=False, repeats=
             log("autotune %s %.3f ms" % (t, ms))
     results.sort(key=lambda x: x[0])
     best_ms, best = results[0]
+    if bmax >= (1 << best["medium_log2"]):
+        # large primes: the bucket-fill workgroup mapping around the best tile setting
+        for extra in bucket_candidates():
+            t = dict(best, **extra)
+            ms = time_batch(ctx, primes, l, outs, t, repeats)
+            results.append((ms, t))
+            if log:
+                log("autotune %s %.3f ms" % (t, ms))
+        results.sort(key=lambda x: x[0])
+        best_ms, best = results[0]
     _store(cache_path, key, {"tune": best, "ms": best_ms, "when": time.strftime("%Y-%m-%d %H:%M:%S"),
                              "tried": [{"tune": t, "ms": m} for (m, t) in results]})
     return dict(best)
