@@ -51,7 +51,8 @@ typedef enum {
     SIEVE_E_NOMEM = -4,   /* device allocation failed                                */
     SIEVE_E_HIP = -5,     /* a HIP runtime call failed (see sieve_last_hip_error)     */
     SIEVE_E_BUDGET = -6,  /* batch scratch would exceed the caller's byte budget      */
-    SIEVE_E_DEVICE = -7   /* a kernel reported a violated invariant (bucket overflow) */
+    SIEVE_E_DEVICE = -7,  /* a kernel reported a violated invariant (bucket overflow) */
+    SIEVE_E_SCRATCH = -8  /* the request needs more than the static scratch array holds */
 } sieve_status;
 
 /* Tuning knobs.  A zero field means "library default".  None of them can change
@@ -158,6 +159,25 @@ int sieve_batch(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, const sieve_
  * control.  Pure host computation. */
 int sieve_batch_scratch_bytes(const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
                               size_t nreq, const sieve_tune *tune, uint64_t *bytes);
+
+/* --- allocation-free one-shot entry point ---
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments, result
+ * and stream behaviour as sieve_init, but the call allocates nothing: no hipMalloc,
+ * hipFree or pinned host memory.  Its device scratch is one static array of 4 MiB
+ * per device (held until the process ends), reached through the address
+ * hipGetSymbolAddress gives for the current device at the first call on that
+ * device (which also creates the library's host-side bookkeeping for it).
+ * Limits: B < 2^20 and below the default medium bound 2^tile_log2 (tile_log2 = l
+ * clamped to [15, 20]), so that every sieving prime stays in LDS and no bucket
+ * storage is needed, and n*2^l <= 2^33 bits (one tile launch).  Requests beyond
+ * these return SIEVE_E_SCRATCH before anything is enqueued.
+ * Every call on one device shares that device's array (the patterns built by one
+ * call are reused by the next): calls that overlap on one device race, so callers
+ * order them (one stream, or events).  Device-side invariant flags of these calls
+ * are not reported (sieve_check_device_errors takes an explicit context). */
+int sieve_init_noalloc(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                       uint32_t *S_dev, uint32_t *counts_dev, void *stream);
 
 /* --- helpers --- */
 /* isqrt(v) for the interval (l, f, n): the bound that makes S an exact prime table. */

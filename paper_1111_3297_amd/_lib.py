@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(HERE, "libsieve.so")
 
 SIEVE_OK = 0
 STATUS = {0: "SIEVE_OK", -1: "SIEVE_E_ARG", -2: "SIEVE_E_RANGE", -3: "SIEVE_E_BOUND",
-          -4: "SIEVE_E_NOMEM", -5: "SIEVE_E_HIP", -6: "SIEVE_E_BUDGET", -7: "SIEVE_E_DEVICE"}
+          -4: "SIEVE_E_NOMEM", -5: "SIEVE_E_HIP", -6: "SIEVE_E_BUDGET", -7: "SIEVE_E_DEVICE",
+          -8: "SIEVE_E_SCRATCH"}
 
 # every exported entry point of include/sieve.h
 EXPORTS = [
@@ -20,7 +21,7 @@ EXPORTS = [
     "sieve_ctx_sieve_with", "sieve_batch", "sieve_batch_scratch_bytes", "sieve_required_bound",
     "sieve_strerror", "sieve_last_hip_error", "sieve_check_device_errors", "sieve_ctx_set_timing",
     "sieve_ctx_kernel_times", "sieve_default_ctx", "sieve_copy_calibration", "sieve_microbench",
-    "sieve_debug_buckets",
+    "sieve_debug_buckets", "sieve_init_noalloc",
 ]
 MB_LDS_OR_RANDOM, MB_LDS_OR_SPREAD, MB_VALU, MB_MOD64 = 0, 1, 2, 3
 
@@ -62,6 +63,7 @@ def load():
     u32, u64, vp, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
     sig = {
         "sieve_init": (i32, [u32, u64, u64, u64, vp, vp, vp]),
+        "sieve_init_noalloc": (i32, [u32, u64, u64, u64, vp, vp, vp]),
         "sieve_ctx_create": (i32, [ctypes.POINTER(vp)]),
         "sieve_ctx_destroy": (i32, [vp]),
         "sieve_ctx_sieve": (i32, [vp, u32, u64, u64, u64, vp, vp, ctypes.POINTER(Tune), vp]),

@@ -55,6 +55,15 @@ def sieve_init(l, f, n, B, S, counts, stream=None):
                                 _stream(stream)), "sieve_init")
 
 
+def sieve_init_noalloc(l, f, n, B, S, counts, stream=None):
+    """Allocation-free one-shot sieve (include/sieve.h: sieve_init_noalloc)."""
+    _require_cuda_i32(S, (n << l) // 32, "S")
+    _require_cuda_i32(counts, n, "counts")
+    L.check(L.load().sieve_init_noalloc(l, f, n, B, ctypes.c_void_p(S.data_ptr()),
+                                        ctypes.c_void_p(counts.data_ptr()), _stream(stream)),
+            "sieve_init_noalloc")
+
+
 class Context:
     """An explicit library context (include/sieve.h: sieve_ctx_*)."""
 

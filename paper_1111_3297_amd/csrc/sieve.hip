@@ -40,12 +40,15 @@ constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or 
 constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
 constexpr uint32_t kMaxCountBins = 32768;      // bins of one count job (its LDS histogram: 128 KB)
 
-// Grow-only device buffer.
+// Grow-only device buffer.  A fixed buffer is a slice of the library's static
+// scratch array: it never grows, and a request beyond its size is an error.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool fixed = false;
   int ensure(size_t n) {
     if (n <= bytes) return SIEVE_OK;
+    if (fixed) return SIEVE_E_SCRATCH;
     if (p) {
       // previous users on any stream must be done before the memory is released
       hipError_t e = hipDeviceSynchronize();
@@ -61,6 +64,7 @@ struct DevBuf {
     return SIEVE_OK;
   }
   void release() {
+    if (fixed) return;
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
@@ -165,6 +169,7 @@ struct sieve_ctx {
   bool pin_pending = false;
   DevBuf pat[32], xpat;
   uint32_t pat_words[32] = {0};
+  bool xpat_ready = false, err_ready = false;   // built / cleared on the device
   sieve_primes own;  // table built by sieve_init / sieve_ctx_sieve
   // timing
   bool timing = false;
@@ -384,7 +389,7 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
 
 // The patterns of 17*19*23, 29*31*37 and 41*43*47 (built once per context).
 int get_xpattern(sieve_ctx* c, hipStream_t s, const uint32_t** xpat) {
-  if (!c->xpat.p) {
+  if (!c->xpat_ready) {
     STCHK(c->xpat.ensure((size_t)sv::kXWordsAll * 4));
     static const uint32_t sets[3][3] = {{17, 19, 23}, {29, 31, 37}, {41, 43, 47}};
     for (int i = 0; i < 3; ++i) {
@@ -399,6 +404,7 @@ int get_xpattern(sieve_ctx* c, hipStream_t s, const uint32_t** xpat) {
         sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->xpat.as<uint32_t>() + sv::kXOff[i], sv::kXPer[i], pp, nw);
       }));
     }
+    c->xpat_ready = true;
   }
   *xpat = c->xpat.as<uint32_t>();
   return SIEVE_OK;
@@ -436,10 +442,11 @@ void launch_tile(const sieve_ctx* c, uint32_t L, hipStream_t s, sv::TileArgs ta)
 
 // Device error word: allocated and cleared once per context.
 int ensure_err(sieve_ctx* c, hipStream_t s) {
-  if (c->err.p) return SIEVE_OK;
+  if (c->err_ready) return SIEVE_OK;
   STCHK(c->err.ensure(64));
   sv::k_fill_u32<<<1, 64, 0, s>>>(c->err.as<uint32_t>(), 16, 0);
   HIPCHK(hipGetLastError());
+  c->err_ready = true;
   return SIEVE_OK;
 }
 
@@ -957,6 +964,7 @@ const char* sieve_strerror(int st) {
     case SIEVE_E_HIP: return "HIP runtime error";
     case SIEVE_E_BUDGET: return "batch exceeds the byte budget";
     case SIEVE_E_DEVICE: return "device kernel reported a violated invariant";
+    case SIEVE_E_SCRATCH: return "request exceeds the static scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -966,7 +974,7 @@ int sieve_last_hip_error(void) { return g_last_hip; }
 int sieve_check_device_errors(sieve_ctx* ctx) {
   if (!ctx) return SIEVE_E_ARG;
   std::lock_guard<std::mutex> g(ctx->mu);
-  if (!ctx->err.p) return SIEVE_OK;
+  if (!ctx->err_ready) return SIEVE_OK;
   uint32_t v = 0;
   if (ctx->has_last) HIPCHK(hipStreamSynchronize(ctx->last_stream));
   HIPCHK(hipMemcpy(&v, ctx->err.p, 4, hipMemcpyDeviceToHost));
@@ -1399,3 +1407,106 @@ int sieve_batch_scratch_bytes(const sieve_primes* pr, uint32_t l, const sieve_re
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of sieve_init.  Its scratch (prime table, generator
+// table, plan, first offsets, patterns, error word) lives in one static device
+// array; the host reaches it only through the address hipGetSymbolAddress
+// returns for the current device.  It serves the requests whose sieving primes
+// all stay in LDS (B below the default medium bound 2^tile_log2, so no buckets)
+// and whose table fits one tile launch (at most four 2^31-bit windows); every
+// such request fits the array below.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+struct NoAllocDev {
+  sieve_ctx* ctx = nullptr;        // its DevBufs are fixed slices of the device's scratch
+  unsigned char* base = nullptr;   // device address of scratch on this device
+};
+std::mutex g_na_mu;
+NoAllocDev g_na[kMaxDevices];
+
+// Largest bound and window count the scratch is laid out for.
+constexpr uint64_t kNaMaxB = (1ull << 20) - 1;
+
+// Carves the fixed buffers of ctx out of [base, base + kScratchBytes); returns
+// SIEVE_E_SCRATCH if the layout does not fit (a build-time constant mistake).
+int carve_noalloc(sieve_ctx* c, unsigned char* base) {
+  size_t off = 0;
+  bool ok = true;
+  auto take = [&](DevBuf& b, size_t n) {
+    off = (off + 255) & ~size_t(255);
+    b.p = base + off;
+    b.bytes = n;
+    b.fixed = true;
+    off += n;
+    if (off > kScratchBytes) ok = false;
+  };
+  const uint64_t tab_ub = pi_upper(kNaMaxB);
+  const uint64_t base_ub = pi_upper(65536);
+  take(c->own.P, (size_t)(tab_ub + 16) * 4);
+  take(c->own.cnt, 16);
+  take(c->gen_blk, (size_t)base_ub * 4 + 64);
+  take(c->plan, sizeof(sv::Plan) * 2);
+  // generator offsets, then every window's medium-prime offsets of the tile launch
+  take(c->Q0, std::max<size_t>((size_t)base_ub * 8, (size_t)sv::kMaxWins * tab_ub * 8 + 64));
+  const uint64_t gbits = 1ull << 19;   // odd numbers below 2^20, whole 2^15-bit count segments
+  const uint64_t nwords = gbits / 32;
+  take(c->gen_S, (size_t)(nwords + (nwords + 1023) / 1024 + (gbits >> 15) + 64) * 4);
+  take(c->err, 64);
+  for (auto& b : c->pat) take(b, (size_t)sv::kPatWordsMax * 4);
+  take(c->xpat, (size_t)sv::kXWordsAll * 4);
+  return ok ? SIEVE_OK : SIEVE_E_SCRATCH;
+}
+
+// Set-up on the first call on a device (that device current): the scratch's
+// device address and a context whose buffers are slices of it.
+int noalloc_setup(int dev, sieve_ctx** out) {
+  std::lock_guard<std::mutex> g(g_na_mu);
+  NoAllocDev& d = g_na[dev];
+  if (!d.ctx) {
+    unsigned char* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+    sieve_ctx* c = new (std::nothrow) sieve_ctx();
+    if (!c) return SIEVE_E_NOMEM;
+    const int rc = carve_noalloc(c, ptr);
+    if (rc != SIEVE_OK) { delete c; return rc; }
+    d.base = ptr;
+    d.ctx = c;
+  }
+  *out = d.ctx;
+  return SIEVE_OK;
+}
+
+}  // namespace
+
+extern "C" int sieve_init_noalloc(uint32_t l, uint64_t f, uint64_t n, uint64_t B, uint32_t* S_dev,
+                                  uint32_t* counts_dev, void* stream) {
+  // argument and size checks come before any HIP call
+  if (!S_dev || !counts_dev) return SIEVE_E_ARG;
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, B, &F, &NB));
+  Resolved R;
+  STCHK(resolve_tune(l, nullptr, &R));
+  if (B >= (1ull << R.Mlog) || B > kNaMaxB) return SIEVE_E_SCRATCH;             // no bucket path
+  if ((NB + kLaunchBits - 1) / kLaunchBits > sv::kMaxWins) return SIEVE_E_SCRATCH;   // one tile launch
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SIEVE_E_ARG;
+  sieve_ctx* c = nullptr;
+  STCHK(noalloc_setup(dev, &c));
+  std::lock_guard<std::mutex> g(c->mu);
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(c, s));
+  STCHK(build_primes(c, B, &c->own, s));
+  STCHK(run_sieve(c, &c->own, l, F, NB, B, S_dev, counts_dev, R, s));
+  return end(c, s);
+}

@@ -51,6 +51,12 @@ def test_argument_errors_without_gpu():
     assert lib.sieve_required_bound(20, 2**39 - 2048, 4096, ctypes.byref(B)) == 0
     assert B.value == 2**30 + 1
     assert _lib.strerror(-3).startswith("sieving bound")
+    # the allocation-free entry point rejects what its static scratch cannot hold
+    assert lib.sieve_init_noalloc(20, 474789, 4, 1 << 20, dummy, dummy, None) == E["SIEVE_E_SCRATCH"]
+    assert lib.sieve_init_noalloc(15, 0, 4, 1 << 15, dummy, dummy, None) == E["SIEVE_E_SCRATCH"]
+    assert lib.sieve_init_noalloc(20, 0, 8193, 1000, dummy, dummy, None) == E["SIEVE_E_SCRATCH"]
+    assert lib.sieve_init_noalloc(20, 0, 1, 1000, None, dummy, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_init_noalloc(10, 0, 1, 2, dummy, dummy, None) == E["SIEVE_E_BOUND"]
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
