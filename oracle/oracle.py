@@ -39,6 +39,9 @@ def _load():
         lib.oracle_sieve.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint64, u32p, u32p]
         lib.oracle_sieve.restype = ctypes.c_int
+        lib.oracle_sieve_with.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                          u32p, ctypes.c_long, u32p, u32p]
+        lib.oracle_sieve_with.restype = ctypes.c_int
         lib.oracle_odd_primes.argtypes = [ctypes.c_uint64, ctypes.POINTER(u32p)]
         lib.oracle_odd_primes.restype = ctypes.c_long
         lib.oracle_lemma1_offset.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
@@ -70,6 +73,22 @@ def sieve(l, f, n, B):
                           c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
     if rc != 0:
         raise OracleError("oracle_sieve(l=%d, f=%d, n=%d, B=%d) -> %d" % (l, f, n, B, rc))
+    return S[:nwords], c[:n]
+
+
+def sieve_with(l, f, n, B, P):
+    """Definition 1 with the odd primes given (ascending uint32 array holding at
+    least every odd prime <= B; larger entries are ignored): (S, counts)."""
+    lib = _load()
+    P = np.ascontiguousarray(P, dtype=np.uint32)
+    nwords = (n << l) // 32
+    S = np.zeros(max(nwords, 1), dtype=np.uint32)
+    c = np.zeros(max(n, 1), dtype=np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    rc = lib.oracle_sieve_with(l, f, n, B, P.ctypes.data_as(u32p), len(P),
+                               S.ctypes.data_as(u32p), c.ctypes.data_as(u32p))
+    if rc != 0:
+        raise OracleError("oracle_sieve_with(l=%d, f=%d, n=%d, B=%d) -> %d" % (l, f, n, B, rc))
     return S[:nwords], c[:n]
 
 

@@ -29,7 +29,8 @@
  *
  * Parity status: pinned (tests/test_oracle_pins.py: trial division on small
  * ranges, Miller-Rabin on sampled bits, known values of pi(x), Lemma 1 by
- * brute force).
+ * brute force; oracle_count_total by pi(2^22) - 1 and the sum of the counts;
+ * oracle_sieve_with by oracle_sieve on prime lists running past B).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -79,19 +80,20 @@ static int oracle_interval(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
     return OR_OK;
 }
 
-/* Definition 1 written out.  S must hold n*2^l/32 words, counts n words. */
-int oracle_sieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
-                 uint32_t *S, uint32_t *counts)
+/* Definition 1 written out, with the odd primes given: P[0..np) ascending
+ * (Section 1.4's base, at least every odd prime <= B); primes above B are not
+ * used.  S must hold n*2^l/32 words, counts n words. */
+int oracle_sieve_with(uint32_t l, uint64_t f, uint64_t n, uint64_t B, const uint32_t *P, long np,
+                      uint32_t *S, uint32_t *counts)
 {
     uint64_t F, NB, u, v;
     int rc = oracle_interval(l, f, n, B, &F, &NB, &u, &v);
     if (rc) return rc;
+    if (np < 0 || (np > 0 && !P)) return OR_E_ARG;
     memset(S, 0, (size_t)(NB / 32) * 4);
-    uint32_t *P = NULL;
-    long np = oracle_odd_primes(B, &P);
-    if (np < 0) return OR_E_NOMEM;
     for (long i = 0; i < np; ++i) {
         uint64_t p = P[i];
+        if (p > B) break;
         /* smallest odd cofactor m >= 3 with m*p >= u */
         u128 m = ((u128)u + p - 1) / p;
         if (m < 3) m = 3;
@@ -101,7 +103,6 @@ int oracle_sieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
         uint64_t j = (uint64_t)((N - u) / 2);
         for (; j < NB; j += p) S[j >> 5] |= 1u << (j & 31);
     }
-    free(P);
     if (u == 1) S[0] |= 1u;                  /* the number 1 is not prime */
     uint64_t wps = ((uint64_t)1 << l) / 32;  /* words per segment */
     for (uint64_t t = 0; t < n; ++t) {
@@ -111,6 +112,21 @@ int oracle_sieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
         counts[t] = (uint32_t)(((uint64_t)1 << l) - ones);
     }
     return OR_OK;
+}
+
+/* Definition 1 written out: the odd primes <= B, then oracle_sieve_with. */
+int oracle_sieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                 uint32_t *S, uint32_t *counts)
+{
+    uint64_t F, NB, u, v;
+    int rc = oracle_interval(l, f, n, B, &F, &NB, &u, &v);
+    if (rc) return rc;
+    uint32_t *P = NULL;
+    long np = oracle_odd_primes(B, &P);
+    if (np < 0) return OR_E_NOMEM;
+    rc = oracle_sieve_with(l, f, n, B, P, np, S, counts);
+    free(P);
+    return rc;
 }
 
 /* Lemma 1 (Section 2.1), in the paper's own steps: with r = f*2^(l+1) mod p the
@@ -132,9 +148,9 @@ uint64_t oracle_lemma2_skip(uint32_t p, uint32_t q, uint32_t l)
     return ((uint64_t)q + p) >> l;
 }
 
-/* Reference batch helper: n31 = number of 2^l-bit segments; same as
- * oracle_sieve but returns only the count total (no table kept) for a sample
- * used by the CPU baseline timing.  Returns -1 on error. */
+/* The sum of the per-segment zero-bit counts of oracle_sieve's table (the
+ * table itself is discarded): the CPU baseline's unit of work.  Returns -1 on
+ * error. */
 long long oracle_count_total(uint32_t l, uint64_t f, uint64_t n, uint64_t B)
 {
     uint64_t NBw = ((uint64_t)n << l) / 32;

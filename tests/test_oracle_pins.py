@@ -194,3 +194,26 @@ def test_invalid_arguments_raise():
         O.sieve(10, 0, 1, 1 << 32)   # B >= 2^32
     with pytest.raises(O.OracleError):
         O.sieve(20, (1 << 43), 1, 3)  # v >= 2^64
+
+
+def test_count_total_equals_sum_of_counts():
+    # the CPU baseline's unit of work: the total of the table's per-segment counts;
+    # 1..2^22 with primes <= 2048 leaves the odd primes below 2^22, pi(2^22) - 1
+    assert O.count_total(15, 0, 64, 2048) == 295946
+    rng = random.Random(5)
+    for _ in range(6):
+        l = rng.choice([5, 9, 12, 14])
+        f = rng.randint(0, 10**6)
+        n = rng.randint(1, 9)
+        u, v = O.interval(l, f, n)
+        B = max(3, math.isqrt(v) // rng.choice([1, 3]))
+        assert O.count_total(l, f, n, B) == int(O.sieve(l, f, n, B)[1].astype(np.int64).sum())
+
+
+def test_sieve_with_given_primes_uses_only_those_up_to_B():
+    # a prime list running past B sieves exactly as the primes <= B alone
+    P = O.odd_primes(5000)
+    for (l, f, n, B) in [(10, 0, 4, 13), (10, 0, 4, 3000), (12, 12345, 3, 997), (14, 10**6, 2, 4999)]:
+        S0, c0 = O.sieve(l, f, n, B)
+        S1, c1 = O.sieve_with(l, f, n, B, P)
+        assert np.array_equal(S0, S1) and np.array_equal(c0, c1), (l, f, n, B)
