@@ -146,7 +146,8 @@ int sieve_ctx_sieve_with(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uin
                          uint64_t n, uint64_t B, uint32_t *S_dev, uint32_t *counts_dev,
                          const sieve_tune *tune, void *stream);
 
-/* --- batched persistent launch ---
+/* --- batched persistent launch (Section 5: sieving combined with parallel
+ * processing, here many intervals of Section 1.2.1 in one launch) ---
  * Sieves every request of reqs[0..nreq) (all with segment size 2^l) against the
  * one shared table pr: one offset kernel, one bucket fill and one persistent tile
  * kernel for the whole batch, whose workgroups take (request, run of up to four
@@ -156,7 +157,9 @@ int sieve_batch(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, const sieve_
                 size_t nreq, const sieve_tune *tune, void *stream);
 /* Device scratch bytes sieve_batch needs for these requests (bucket storage and
  * per-request state; not counting the caller's S and counts), for admission
- * control.  Pure host computation. */
+ * control.  The bucket part follows the hit count of Sections 2.2-2.3 (a prime p
+ * hits a span of s bits about s/p times; summed over the large primes).  Pure host
+ * computation. */
 int sieve_batch_scratch_bytes(const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
                               size_t nreq, const sieve_tune *tune, uint64_t *bytes);
 
@@ -180,7 +183,8 @@ int sieve_init_noalloc(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
                        uint32_t *S_dev, uint32_t *counts_dev, void *stream);
 
 /* --- helpers --- */
-/* isqrt(v) for the interval (l, f, n): the bound that makes S an exact prime table. */
+/* isqrt(v) for the interval (l, f, n): the bound that makes S an exact prime table
+ * (Section 1.4: sieving with the primes up to sqrt(v) leaves exactly the primes). */
 int sieve_required_bound(uint32_t l, uint64_t f, uint64_t n, uint64_t *B);
 const char *sieve_strerror(int status);
 /* The last hipError_t seen by the library on this thread (0 if none). */

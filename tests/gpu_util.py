@@ -17,10 +17,13 @@ def gpu_sieve(l, f, n, B, tune=None, ctx=None, primes=None):
     S, c = api.alloc(l, n)
     if ctx is None and tune is None and primes is None:
         api.sieve_init(l, f, n, B, S, c)
+        ctx = api.Context.default()
     else:
         ctx = ctx or api.Context()
         ctx.sieve(l, f, n, B, S, c, tune=tune, primes=primes)
     torch.cuda.synchronize()
+    # the device error word (bucket overflow, prime-table overflow) must be clear
+    ctx.check_device_errors()
     return S.cpu().numpy().view(np.uint32), c.cpu().numpy().view(np.uint32)
 
 

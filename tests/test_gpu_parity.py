@@ -54,6 +54,24 @@ def test_near_2_64_partial_sieve():
     check_case(20, 2**43 - 3, 2, 3)
 
 
+def test_near_2_64_bucket_path():
+    # large primes (p >= 2^20 at the default tuning) with first hits computed from
+    # a 64-bit start near 2^63 (G0 = f*2^20)
+    check_case(20, 2**43 - 4, 3, 3 * 10**6)
+    # the bucket path forced on with a small medium bound: 16- and 32-bit entries,
+    # several chunks per launch
+    check_case(20, 2**43 - 3, 2, 10**6, tune={"tile_log2": 15, "medium_log2": 11, "bins_log2": 8})
+    check_case(17, 2**46 - 40, 32, 2 * 10**6,
+               tune={"tile_log2": 17, "medium_log2": 14, "bins_log2": 8, "bin_log2": 17, "groups": 96})
+
+
+@pytest.mark.parametrize("groups", [1024, 4096])
+def test_bucket_fill_workgroup_counts(groups):
+    # the bucket-fill workgroup counts the batch autotuner may pick, on the plain path
+    l, f, n = 20, (10**14) >> 21, 24
+    check_case(l, f, n, math.isqrt(O.interval(l, f, n)[1]), tune={"groups": groups})
+
+
 def test_random_small_with_tunings():
     rng = random.Random(20111111)
     tunings = [None,
@@ -209,10 +227,28 @@ def _golden(name):
         return json.load(fh)
 
 
-@pytest.mark.parametrize("name", ["interval_1e12", "interval_1e12_b6", "interval_2p60", "interval_3win"])
+@pytest.mark.parametrize("name", ["interval_1e12", "interval_1e12_b6", "interval_2p60", "interval_3win",
+                                  "serve_req71", "serve_req6388", "interval_2p64_top"])
 def test_full_size_against_oracle_golden(name):
     g = _golden(name)
     say("full size", name, g["l"], g["f"], g["n"], g["B"])
     S, c = gpu_sieve(g["l"], g["f"], g["n"], g["B"])
     assert [int(x) for x in c] == g["counts"]
     assert sha256_words(S) == g["S_sha256"]
+
+
+@pytest.mark.parametrize("B", [2133783848, 4294967295])
+def test_prime_table_against_oracle_golden(B):
+    # the largest bound the serving stream uses, and the largest the interface allows
+    import hashlib
+    import torch
+    from paper_1111_3297_amd import api
+    g = _golden("primes_%d" % B)
+    say("prime table golden B=%d" % B)
+    pr = api.Primes(B)
+    assert pr.count == g["count"], (pr.count, g["count"])
+    got = pr.to_tensor().cpu().numpy().view(np.uint32)
+    torch.cuda.synchronize()
+    assert int(got[-1]) == g["max"]
+    assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == g["sha256"]
+    pr.close()

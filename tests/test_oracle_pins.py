@@ -96,13 +96,18 @@ def test_brute_force_small_intervals():
             assert c[t] == seg - int(want[t * seg:(t + 1) * seg].sum())
 
 
-def test_pi_values_from_published_table():
+def pi_table():
     vals = []
     with open(os.path.join(HERE, "golden", "pi_values.txt")) as fh:
         for line in fh:
             line = line.split("#")[0].split()
             if line:
-                vals.append((int(line[0]), int(line[1])))
+                vals.append((int(line[0]), int(line[1]), len(line) > 2 and line[2] == "golden"))
+    return vals
+
+
+def test_pi_values_from_published_table():
+    vals = [(x, pi) for (x, pi, big) in pi_table() if not big]
     for x, pi in vals:
         # base-prime generator: odd primes <= x plus the prime 2
         assert len(O.odd_primes(x)) + 1 == pi, x
@@ -217,3 +222,17 @@ def test_sieve_with_given_primes_uses_only_those_up_to_B():
         S0, c0 = O.sieve(l, f, n, B)
         S1, c1 = O.sieve_with(l, f, n, B, P)
         assert np.array_equal(S0, S1) and np.array_equal(c0, c1), (l, f, n, B)
+
+
+def test_prime_table_goldens_match_published_pi():
+    # the oracle's odd primes <= 2^32 - 1 (written once by make_golden.py) number
+    # pi(2^32) - 1; below 2^31 + 1 they number pi(2^31) - 1
+    import json
+    pub = {x: pi for (x, pi, _) in pi_table()}
+    g = json.load(open(os.path.join(HERE, "golden", "primes_4294967295.json")))
+    assert g["count"] + 1 == pub[4294967296] and g["max"] == 4294967291
+    # 2133783848 lies below 2^31: its count is at most pi(2^31) - 1 and the table is
+    # the prefix of the 2^32 one (checked on the GPU); the count is the survey's
+    # independent cross-check value
+    g2 = json.load(open(os.path.join(HERE, "golden", "primes_2133783848.json")))
+    assert g2["count"] == 104459685 and g2["count"] + 1 <= pub[2147483648]
