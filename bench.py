@@ -1,15 +1,22 @@
 """Benchmark: sieved numbers per second of the segmented odd-only sieve on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload interval_1e12]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch_1234]
 
-A step is one full sieve_init call on the workload: device prime generation up to
-B, first offsets, the large-prime bucket fill (when B reaches the bucket range),
-every LDS tile (pattern, medium primes, bucket drain, write-out with popcounts).
-Inputs are interval parameters; outputs land in HBM.  The line printed is one
-JSON object.  Its roofline entry rates the tile kernel by algorithmic marks (every
-odd multiple of every prime 17 <= p <= B in the interval, at or above p^2) per
-second against one 32-bit LDS access per bank per clock on every CU; its
-cpu_baseline entry times the plain CPU oracle on the same interval.
+The headline workload is the batch of 256 seeded interval requests (seed 1234,
+centres log-uniform in [1e6, 1e15], widths log-uniform in [2^20, 2^30] numbers, B =
+isqrt(v) each) sieved against one shared prime table.  A step is one sieve_batch
+call over all 256 requests: first offsets, the large-prime bucket fill, every LDS
+tile (pattern, medium primes, bucket drain, write-out with popcounts); the plain
+per-interval kernel looped over the same requests is timed beside it.  A plain
+workload name (interval_2p22, interval_1e12, interval_1e12_b6, interval_2p60)
+makes a step one sieve_init call on that interval instead.
+
+The printed line is one JSON object: the headline, its roofline (the dominant
+kernel's algorithmic work per launch over its measured launch time), the plain
+workloads with their own rooflines (the LDS-bound tile kernel at 1e12, the
+HBM-bound bucket scatter at 2^60), launch latency of the small interval, the
+serving replays (checked against the oracle's values) and the CPU oracle timed on
+the host's cores.
 """
 import argparse
 import hashlib
@@ -24,8 +31,9 @@ sys.path.insert(0, ROOT)
 
 # MI355X figures used for the roofline.
 CUS, CLOCK_HZ = 256, 2.4e9
-LDS_PEAK_OPS = CUS * CLOCK_HZ * 32          # one 32-bit LDS access per bank per clock, 32 banks
-HBM_PEAK = 8.0e12                           # bytes/s
+LDS_PEAK_OPS = CUS * CLOCK_HZ * 32          # one 32-bit access per LDS bank per clock, 32 banks per CU
+HBM_PEAK = 8.0e12                           # bytes/s, published HBM3E peak
+BUCKET_BYTES_PER_HIT = 8                    # the method's bucket entry (prime, offset), written once per hit
 
 
 def marks_algorithmic(primes, u, v):
@@ -103,49 +111,162 @@ def traffic_from_profile(workload, kernel):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(l, f, n, B, budget_s=12.0):
-    """The CPU oracle (single-threaded plain C) on a bounded prefix of the workload."""
+def host_info():
+    """Host cores this process may use and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model}
+
+
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def cpu_baseline_batch(reqs, l=20, budget_s=12.0):
+    """The CPU oracle (single-threaded plain C) on the batch's requests in batch order
+    until about budget_s seconds have passed; every total is checked against the
+    oracle's golden for the batch."""
     from oracle import oracle as O
     O.build()
-    # calibrate on a small prefix, then run a prefix sized to the budget
+    g = _golden("batch_1234")
+    t = time.perf_counter()
+    numbers, done, ok = 0, 0, True
+    for k, (f, n, B) in enumerate(reqs):
+        tot = O.count_total(l, f, n, B)
+        if g is not None and tot != g["requests"][k]["total"]:
+            ok = False
+        numbers += n << (l + 1)
+        done += 1
+        if time.perf_counter() - t >= budget_s:
+            break
+    dt = time.perf_counter() - t
+    return {"value": numbers / dt, "unit": "numbers/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %d of the %d batch requests in batch order (%d numbers), %.1f s" % (done, len(reqs),
+                                                                                                  numbers, dt),
+            "totals_match_golden": ok if g is not None else None}
+
+
+def cpu_baseline_batch_all_cores(reqs, l=20, per_proc_s=8.0, one_core_rate=None):
+    """The same oracle in one process per usable host core (at most 16), the batch's
+    requests dealt round-robin, as many of them as take about per_proc_s seconds per
+    process at the single-core rate; timed from the first start to the last end."""
+    import subprocess
+    procs = max(1, min(16, host_info()["usable_cores"] or 1))
+    rate = one_core_rate or 5e8
+    want = rate * per_proc_s * procs
+    take, acc = [], 0
+    for r in reqs:
+        take.append(r)
+        acc += r[1] << (l + 1)
+        if acc >= want:
+            break
+    code = ("import sys, json; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "js = json.loads(sys.argv[1]); print(json.dumps([O.count_total(%d, f, n, B) for (f, n, B) in js]))"
+            % (ROOT, l))
+    parts = [take[k::procs] for k in range(procs)]
+    t = time.perf_counter()
+    ps = [subprocess.Popen([sys.executable, "-c", code, json.dumps(p)], stdout=subprocess.PIPE) for p in parts]
+    outs = [q.communicate()[0] for q in ps]
+    wall = time.perf_counter() - t
+    if any(q.returncode for q in ps):
+        return None
+    g = _golden("batch_1234")
+    ok = None
+    if g is not None:
+        index = {(r["f"], r["n"], r["B"]): r["total"] for r in g["requests"]}
+        ok = all(index.get(tuple(r)) == tot for p, o in zip(parts, outs) for r, tot in zip(p, json.loads(o)))
+    return {"value": acc / wall, "unit": "numbers/s", "cores": procs, "kind": "oracle",
+            "sample": "the first %d batch requests (%d numbers) dealt round-robin to %d processes, %.1f s"
+                      % (len(take), acc, procs, wall), "totals_match_golden": ok}
+
+
+def cpu_baseline_plain(l, f, n, B, budget_s=12.0):
+    """The CPU oracle (single-threaded plain C) on a bounded prefix of a plain interval."""
+    from oracle import oracle as O
+    O.build()
     n0 = max(1, min(n, 16))
     t = time.perf_counter()
     O.count_total(l, f, n0, B)
     dt0 = time.perf_counter() - t
     ns = max(n0, min(n, int(n0 * budget_s / max(dt0, 1e-3))))
     t = time.perf_counter()
-    O.count_total(l, f, ns, B)
+    tot = O.count_total(l, f, ns, B)
     dt = time.perf_counter() - t
     numbers = ns * (1 << (l + 1))
     return {"value": numbers / dt, "unit": "numbers/s", "cores": 1, "kind": "oracle",
             "sample": "first %d of %d segments (%d numbers) of the same interval and bound, %.1f s"
-                      % (ns, n, numbers, dt)}
+                      % (ns, n, numbers, dt), "zero_bits": tot}
 
 
-def cpu_baseline_all_cores(l, f, n, B, per_proc_s=8.0):
-    """The same oracle in one process per host core (at most 16), each on its own contiguous
-    range of segments of the workload, timed from the first start to the last end."""
-    import subprocess
-    from oracle import oracle as O
-    O.build()
-    procs = max(1, min(16, os.cpu_count() or 1))
-    n0 = max(1, min(n, 8))
-    t = time.perf_counter()
-    O.count_total(l, f, n0, B)
-    per_seg = max(time.perf_counter() - t, 1e-6) / n0
-    each = max(1, min(n // procs, int(per_proc_s / per_seg)))
-    code = ("import sys; sys.path.insert(0, %r); from oracle import oracle as O; "
-            "O.count_total(%d, int(sys.argv[1]), %d, %d)" % (ROOT, l, each, B))
-    t = time.perf_counter()
-    ps = [subprocess.Popen([sys.executable, "-c", code, str(f + k * each)]) for k in range(procs)]
-    rcs = [q.wait() for q in ps]
-    wall = time.perf_counter() - t
-    if any(rcs):
-        return None
-    numbers = procs * each * (1 << (l + 1))
-    return {"value": numbers / wall, "unit": "numbers/s", "cores": procs, "kind": "oracle",
-            "sample": "segments %d..%d of %d (%d numbers) of the same interval and bound, %d processes of %d "
-                      "segments, %.1f s" % (0, procs * each - 1, n, numbers, procs, each, wall)}
+def roofline_lds(kernel, marks_per_launch, per_launch_ms, traffic, rates=None, executed=None):
+    achieved = marks_per_launch / (per_launch_ms * 1e-3)
+    out = {"bound": "lds", "kernel": kernel, "achieved": achieved / 1e9, "peak": LDS_PEAK_OPS / 1e9,
+           "unit": "Gmarks/s", "frac": achieved / LDS_PEAK_OPS, "traffic": traffic,
+           "per_launch": {"algorithmic_marks": marks_per_launch, "avg_ms": per_launch_ms}}
+    if rates is not None:
+        # against the measured conflict-free LDS atomic rate, and the executed atomics
+        # (wheel and masks leave about half the marks out) against the random-address rate
+        out["frac_of_measured_conflict_free_lds"] = achieved / rates["lds_or_spread_per_s"]
+        if executed is not None:
+            out["executed_marks"] = executed
+            out["executed_frac_of_measured_random_lds"] = executed / (per_launch_ms * 1e-3) / rates["lds_or_random_per_s"]
+    return out
+
+
+def roofline_hbm(kernel, bytes_per_launch, per_launch_ms, traffic, what):
+    achieved = bytes_per_launch / (per_launch_ms * 1e-3)
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": traffic,
+            "per_launch": {"algorithmic_bytes": bytes_per_launch, "avg_ms": per_launch_ms, "what": what}}
+
+
+def _kernel_times(ctx, fn, steps):
+    """Per-kernel milliseconds per step over `steps` calls, with an event pair around
+    every launch (on the stream it is launched on)."""
+    import torch
+    ctx.kernel_times()
+    ctx.set_timing(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    kt = ctx.kernel_times()
+    ctx.set_timing(False)
+    return {k: {"total_ms": ms / steps, "launches_per_step": nl / steps} for k, (ms, nl) in kt.items()}
+
+
+def _step_times(fn, steps, stream):
+    """Milliseconds of each call, one event pair per call and nothing else."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in ev], wall
+
+
+def _pct(xs, q):
+    ys = sorted(xs)
+    return ys[min(len(ys) - 1, max(0, int(math.ceil(q * len(ys))) - 1))]
 
 
 def run_plain(name, steps, warmup, check=True):
@@ -157,52 +278,29 @@ def run_plain(name, steps, warmup, check=True):
     S, c = api.alloc(l, n)
     ctx = api.Context.default()
     stream = torch.cuda.current_stream()
+    call = lambda: api.sieve_init(l, f, n, B, S, c)
     for _ in range(warmup):
-        api.sieve_init(l, f, n, B, S, c)
+        call()
     torch.cuda.synchronize()
-    # the timed steps: one event pair per step and nothing else on the stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        api.sieve_init(l, f, n, B, S, c)
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = sorted(a.elapsed_time(b) for a, b in ev)
-    # the same steps again with an event pair around every kernel launch (on the
-    # stream it is launched on), for the per-kernel durations and the roofline
-    ctx.kernel_times()                     # drop anything recorded so far
-    ctx.set_timing(True)
-    ek = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    for a, b in ek:
-        a.record(stream)
-        api.sieve_init(l, f, n, B, S, c)
-        b.record(stream)
-    torch.cuda.synchronize()
-    kt = ctx.kernel_times()
-    ctx.set_timing(False)
-    step_ms_kev = sum(a.elapsed_time(b) for a, b in ek) / steps
+    lat, wall = _step_times(call, steps, stream)
+    kernels = _kernel_times(ctx, call, steps)
     step_ms = sum(lat) / len(lat)
-    numbers = v - u + 1
     out = {"name": name, "l": l, "f": f, "n": n, "B": B, "u": u, "v": v,
            "ms_per_step": step_ms, "wall_ms_per_step": 1e3 * wall / steps,
-           "ms_per_step_with_kernel_events": step_ms_kev,
-           "numbers_per_s": numbers / (step_ms * 1e-3),
-           "p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
-           "kernels": {k: {"total_ms": ms / steps, "launches_per_step": nl / steps} for k, (ms, nl) in kt.items()}}
+           "numbers_per_s": (v - u + 1) / (step_ms * 1e-3), "p50_ms": _pct(lat, 0.5), "p99_ms": _pct(lat, 0.99),
+           "kernels": kernels}
     if check:
-        gpath = os.path.join(ROOT, "tests", "golden", name + ".json")
-        if os.path.exists(gpath):
-            with open(gpath) as fh:
-                g = json.load(fh)
+        g = _golden(name)
+        if g is not None:
             Sh = S.cpu().numpy().view(np.uint32)
             ch = c.cpu().numpy().view(np.uint32)
             out["bit_exact"] = bool(hashlib.sha256(Sh.tobytes()).hexdigest() == g["S_sha256"]
                                     and [int(x) for x in ch] == g["counts"])
+        elif name == "interval_2p22":
+            out["bit_exact"] = int(c.cpu().numpy().view(np.uint32).astype(np.int64).sum()) + 1 == 295947
         else:
             out["bit_exact"] = None
+    ctx.check_device_errors()
     pr = api.Primes(B)
     out["_primes"] = pr.to_tensor().cpu().numpy().view(np.uint32)
     torch.cuda.synchronize()
@@ -210,17 +308,56 @@ def run_plain(name, steps, warmup, check=True):
     return out
 
 
-def run_batch_bench(steps, log):
-    """The 256-request batch (seed 1234, B = isqrt(v) each): one persistent batched
-    launch per step against looping the plain per-interval sieve."""
+def run_latency(steps):
+    """Launch latency of the small interval (1 .. 2^22, primes <= 2048): each call
+    alone, waited for; device time (event pair) and host time (call to completion)."""
     import numpy as np
     import torch
-    from paper_1111_3297_amd import api, autotune, workloads
-    l = 20
+    from paper_1111_3297_amd import api, workloads
+    l, f, n, B = workloads.plain_configs()["interval_2p22"]
+    S, c = api.alloc(l, n)
+    stream = torch.cuda.current_stream()
+    for _ in range(20):
+        api.sieve_init(l, f, n, B, S, c)
+    torch.cuda.synchronize()
+    dev, host = [], []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(steps):
+        t = time.perf_counter()
+        a.record(stream)
+        api.sieve_init(l, f, n, B, S, c)
+        b.record(stream)
+        b.synchronize()
+        host.append(1e3 * (time.perf_counter() - t))
+        dev.append(a.elapsed_time(b))
+    ok = int(c.cpu().numpy().view(np.uint32).astype(np.int64).sum()) + 1 == 295947
+    return {"workload": "interval_2p22: l=15 f=0 n=64 B=2048 (sieves 1..2^22)", "calls": steps,
+            "device_p50_ms": _pct(dev, 0.5), "device_p99_ms": _pct(dev, 0.99),
+            "host_p50_ms": _pct(host, 0.5), "host_p99_ms": _pct(host, 0.99), "pi_2p22_ok": ok}
+
+
+BATCH_WORKLOAD = ("batch_1234: 256 interval requests, seed 1234, centres log-uniform in [1e6, 1e15], widths "
+                  "log-uniform in [2^20, 2^30] numbers in whole 2^21-number blocks (l=20), B = isqrt(v) each, one "
+                  "shared prime table up to isqrt(max v)")
+
+
+def batch_requests(l=20):
+    from paper_1111_3297_amd import workloads
     reqs = []
     for f21, n21 in workloads.batch_requests(1234, 256):
         u, v = workloads.interval(l, f21, n21)
         reqs.append((f21, n21, math.isqrt(v)))
+    return reqs
+
+
+def run_batch(steps, warmup, log, loops=2):
+    """The 256-request batch: one persistent batched launch per step, against looping
+    the plain per-interval sieve over the same requests."""
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api, autotune
+    l = 20
+    reqs = batch_requests(l)
     numbers = sum(n << (l + 1) for (_, n, _) in reqs)
     pr = api.Primes(max(B for (_, _, B) in reqs))
     outs = []
@@ -232,23 +369,16 @@ def run_batch_bench(steps, log):
     tune = autotune.tune_batch(pr, l, outs, ctx=ctx, log=log)
     tune_s = time.perf_counter() - t
     stream = torch.cuda.current_stream()
-
-    def timed(fn, k):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(k):
-            fn()
-        b.record(stream)
-        b.synchronize()
-        return a.elapsed_time(b) / k
-
-    ms_batch = timed(lambda: ctx.batch(pr, l, outs, tune=tune), steps)
+    call = lambda: ctx.batch(pr, l, outs, tune=tune)
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    lat, wall = _step_times(call, steps, stream)
+    kernels = _kernel_times(ctx, call, max(2, steps // 4))
+    ms = sum(lat) / len(lat)
     bit_exact = None
-    gpath = os.path.join(ROOT, "tests", "golden", "batch_1234.json")
-    if os.path.exists(gpath):
-        g = json.load(open(gpath))
+    g = _golden("batch_1234")
+    if g is not None:
         bit_exact = True
         for (f, n, B, S, c), r in zip(outs, g["requests"]):
             ch = c.cpu().numpy().view(np.uint32)
@@ -265,40 +395,85 @@ def run_batch_bench(steps, log):
         for (f, n, B, S, c) in outs:
             api.sieve_init(l, f, n, B, S, c)
 
-    ms_loop = timed(plain_loop, 2)
-    ms_init = timed(init_loop, 1)
+    plain_loop()
+    pl, _ = _step_times(plain_loop, loops, stream)
+    init_loop()
+    il, _ = _step_times(init_loop, 1, stream)
     ctx.check_device_errors()
-    return {"workload": "256 requests, seed 1234: centres log-uniform in [1e6, 1e15], widths log-uniform in "
-                        "[2^20, 2^30] numbers in whole 2^21-number blocks, B = isqrt(v) each (l=20)",
-            "numbers": numbers, "tune": tune, "autotune_s": round(tune_s, 2),
-            "batched": {"ms": ms_batch, "numbers_per_s": numbers / (ms_batch * 1e-3)},
+    ms_loop, ms_init = sum(pl) / len(pl), sum(il) / len(il)
+    primes = pr.to_tensor().cpu().numpy().view(np.uint32)
+    torch.cuda.synchronize()
+    return {"reqs": reqs, "numbers": numbers, "tune": tune, "autotune_s": round(tune_s, 2), "ms_per_step": ms,
+            "wall_ms_per_step": 1e3 * wall / steps, "numbers_per_s": numbers / (ms * 1e-3),
+            "p50_ms": _pct(lat, 0.5), "p99_ms": _pct(lat, 0.99), "kernels": kernels, "bit_exact": bit_exact,
             "plain_loop_shared_table": {"ms": ms_loop, "numbers_per_s": numbers / (ms_loop * 1e-3)},
             "plain_loop_sieve_init": {"ms": ms_init, "numbers_per_s": numbers / (ms_init * 1e-3)},
-            "speedup_vs_plain_loop": ms_loop / ms_batch, "bit_exact": bit_exact}
+            "speedup_vs_plain_loop": ms_loop / ms, "_primes": primes}
 
 
-def run_serving_bench(seconds, tune, slots=3):
-    """Open-loop replay of the seeded Poisson stream (seed 99, 200 requests/s,
-    90% as in the batch workload, 10% of width 2^28 centred in [1e16, 2^62]) for the
-    first `seconds` seconds, 64 GB budget: continuous batching against a first come
-    first served plain-kernel server."""
+def batch_work(primes, reqs, tune, l=20):
+    """Algorithmic marks (every prime 17 <= p <= B_i) and large-prime hits (primes at or
+    above the tuned medium bound) summed over the batch's requests."""
+    import numpy as np
+    med = 1 << int(tune.get("medium_log2") or tune.get("tile_log2") or 20)
+    marks = hits = 0.0
+    for (f, n, B) in reqs:
+        u, v = f * (1 << (l + 1)) + 1, (f + n) * (1 << (l + 1))
+        P = primes[: int(np.searchsorted(primes, B, side="right"))]
+        marks += marks_algorithmic(P, u, v)
+        hits += large_hits(P, u, v, med)
+    return marks, hits
+
+
+def serving_check(res, g):
+    """Every served request's zero-bit total and counts digest against the oracle's."""
+    import numpy as np
+    if g is None:
+        return None
+    for rid, r in res.items():
+        c = r["counts"]
+        want = g["requests"][rid]
+        if int(c.astype(np.int64).sum()) != want[0] or \
+                hashlib.sha256(c.astype("<u4").tobytes()).hexdigest()[:16] != want[1]:
+            return False
+    return True
+
+
+def run_serving(seconds, speedups, tune, log, slots=3):
+    """Open-loop replays of the seeded Poisson stream (seed 99, 200 requests/s for 60 s,
+    90% as in the batch workload, 10% of width 2^28 centred in [1e16, 2^62]), 64 GB
+    budget: continuous batching against a first-come-first-served plain-kernel
+    server, at the stated rate over `seconds` and time-compressed by each speedup.
+    Every served request's counts are checked against the oracle's golden values."""
     from paper_1111_3297_amd import api, serve
     l = 20
-    reqs = serve.serving_requests(l=l, limit_s=seconds)
-    pr = api.Primes(max(r.B for r in reqs))
+    g = _golden("serve_99")
+    base = serve.serving_requests(l=l, limit_s=seconds)
+    pr = api.Primes(max(r.B for r in base))
     ex = serve.GpuExecutor(pr, l, slots=slots, tune=tune)
     ex0 = serve.PlainExecutor(pr, l)
     # both servers first replay the opening half second untimed (allocator and pinned
     # host memory warm-up), so that neither pays it inside its measured replay
-    warm = [r for r in reqs if r.arrival < 0.5]
+    warm = [r for r in base if r.arrival < 0.5]
     serve.Server(ex, l=l, budget_bytes=64 << 30).run(warm)
     serve.Server(ex0, l=l, budget_bytes=64 << 30, max_group=1).run(warm)
-    _, st = serve.Server(ex, l=l, budget_bytes=64 << 30).run(reqs)
-    _, st0 = serve.Server(ex0, l=l, budget_bytes=64 << 30, max_group=1).run(reqs)
     keep = ("requests", "numbers", "span_s", "numbers_per_s", "p50_ms", "p99_ms", "max_ms", "peak_bytes")
-    return {"workload": "Poisson stream seed 99, 200 req/s, first %g s of 60 s, B = isqrt(v), 64 GB budget" % seconds,
-            "continuous_batching": {k: st[k] for k in keep},
-            "plain_fcfs": {k: st0[k] for k in keep}}
+    out = {"workload": "Poisson stream seed 99, 200 req/s for %g s (12040 requests over the full 60 s), 90%% as the "
+                       "batch, 10%% width 2^28 centred in [1e16, 2^62], B = isqrt(v), 64 GB budget" % seconds,
+           "slots": slots, "replays": []}
+    for sp in [1.0] + list(speedups):
+        reqs = base if sp == 1.0 else serve.serving_requests(l=l, limit_s=seconds, speedup=sp)
+        rec = {"speedup": sp, "offered_req_per_s": 200.0 * sp}
+        for name, exe, mg in (("continuous_batching", ex, 64), ("plain_fcfs", ex0, 1)):
+            prog = (lambda now, done, tot, name=name, sp=sp: log("serving x%g %s: %.0f s, %d of %d done"
+                                                                  % (sp, name, now, done, tot)))
+            res, st = serve.Server(exe, l=l, budget_bytes=64 << 30, max_group=mg, progress=prog).run(reqs)
+            rec[name] = {k: st[k] for k in keep}
+            rec[name]["bit_exact_counts"] = serving_check(res, g)
+            log("serving x%g %s: p50 %.3f ms p99 %.3f ms, %.3g numbers/s" % (sp, name, st["p50_ms"], st["p99_ms"],
+                                                                            st["numbers_per_s"]))
+        out["replays"].append(rec)
+    return out
 
 
 def unit_rates():
@@ -328,28 +503,60 @@ def unit_rates():
     e1.synchronize()
     rates["hbm_copy_bytes_per_s"] = 5 * 2.0 * nb / (e0.elapsed_time(e1) * 1e-3)   # bytes read + written
     del a, b
-    clk_cu = 2.4e9 * 256
+    clk_cu = CLOCK_HZ * CUS
     rates["per_clock_per_cu"] = {"lds_or_random": rates["lds_or_random_per_s"] / clk_cu,
                                  "lds_or_spread": rates["lds_or_spread_per_s"] / clk_cu,
                                  "valu_int32": rates["valu_int32_per_s"] / clk_cu}
     return rates
 
 
+def plain_rooflines(rec, rates):
+    """The roofline of a plain workload's dominant kernel: the tile kernel by LDS marks,
+    or the bucket scatter by the method's bucket bytes."""
+    primes = rec.pop("_primes")
+    u, v = rec["u"], rec["v"]
+    ks = rec["kernels"]
+    dom = max(ks, key=lambda k: ks[k]["total_ms"])
+    out = {}
+    if "k_bucket_scatter" in ks:
+        hits = large_hits(primes, u, v, 1 << 20)
+        kt = ks["k_bucket_scatter"]
+        per_ms = kt["total_ms"] / kt["launches_per_step"]
+        out["k_bucket_scatter"] = roofline_hbm("k_bucket_scatter", BUCKET_BYTES_PER_HIT * hits / kt["launches_per_step"],
+                                               per_ms, traffic_from_profile(rec["name"], "k_bucket_scatter"),
+                                               "%d bytes per large-prime hit (%.4g hits per step)"
+                                               % (BUCKET_BYTES_PER_HIT, hits))
+    kt = ks.get("k_tile")
+    if kt:
+        per_ms = kt["total_ms"] / kt["launches_per_step"]
+        marks = marks_algorithmic(primes, u, v) / kt["launches_per_step"]
+        ex = marks_executed(primes, u, v) / kt["launches_per_step"] if rec["l"] == 20 and rates else None
+        out["k_tile"] = roofline_lds("k_tile", marks, per_ms, traffic_from_profile(rec["name"], "k_tile"), rates, ex)
+    rec["dominant_kernel"] = dom
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="interval_1e12")
+    ap.add_argument("--workload", default="batch_1234", help="batch_1234 (headline) or a plain interval workload")
+    ap.add_argument("--also", default="interval_1e12,interval_2p60", help="comma list of plain workloads to report")
+    ap.add_argument("--latency-steps", type=int, default=200, help="calls of the small interval for launch latency")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="seconds of the request stream to replay (0: skip)")
+    ap.add_argument("--serve-speedups", default="10,30,100", help="time-compressed replays of the same stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--also", default="interval_2p60", help="comma list of extra plain workloads to report")
-    ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches (0: skip the batch bench)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of the request stream to replay (0: skip)")
     ap.add_argument("--no-unit-rates", action="store_true", help="skip the LDS / VALU / copy microbenchmarks")
     ap.add_argument("--unit-rates-only", action="store_true", help="only run the microbenchmarks and print their rates")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run the library's plain copy kernel over this many bytes, 5 times (counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(a sharded run would split each interval into contiguous segment ranges, or route whole "
+              "requests, one GPU each); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         import torch
         from paper_1111_3297_amd import _lib
@@ -367,72 +574,86 @@ def main():
     if args.unit_rates_only:
         print(json.dumps({"unit_rates": unit_rates()}), flush=True)
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: there is no multi-GPU path "
-              "(a sharded run would split the interval into contiguous segment ranges, one per GPU); "
-              "use --gpus 1", file=sys.stderr)
-        sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    main_rec = run_plain(args.workload, args.steps, args.warmup)
-    primes = main_rec.pop("_primes")
-    u, v = main_rec["u"], main_rec["v"]
-    marks = marks_algorithmic(primes, u, v)
-    kt = main_rec["kernels"].get("k_tile", {"total_ms": float("nan"), "launches_per_step": 1})
-    per_launch_ms = kt["total_ms"] / kt["launches_per_step"]
-    marks_per_launch = marks / kt["launches_per_step"]
-    achieved = marks_per_launch / (per_launch_ms * 1e-3)
-    traffic = traffic_from_profile(args.workload, "k_tile")
-    roof = {"bound": "lds", "kernel": "k_tile", "achieved": achieved / 1e9, "peak": LDS_PEAK_OPS / 1e9,
-            "unit": "Gmarks/s", "frac": achieved / LDS_PEAK_OPS, "traffic": traffic,
-            "per_launch": {"marks": marks_per_launch, "avg_ms": per_launch_ms,
-                           "launches_per_step": kt["launches_per_step"]}}
-    rates = None if args.no_unit_rates else unit_rates()
-    if rates is not None and main_rec["l"] == 20:
-        # the LDS atomics actually issued (wheel and masks leave out about half the
-        # algorithmic marks) against the measured random-address ds_or_b32 rate
-        ex = marks_executed(primes, u, v) / kt["launches_per_step"]
-        roof["vs_measured_lds"] = {"executed_marks": ex, "executed_per_s": ex / (per_launch_ms * 1e-3),
-                                   "lds_or_random_per_s": rates["lds_or_random_per_s"],
-                                   "frac": ex / (per_launch_ms * 1e-3) / rates["lds_or_random_per_s"]}
-    also = {}
-    for name in [x for x in args.also.split(",") if x and x != "none"]:
-        rec = run_plain(name, max(3, args.steps // 4), 2)
-        pr = rec.pop("_primes")
-        rec["large_prime_hits"] = large_hits(pr, rec["u"], rec["v"], 1 << 20)
-        also[name] = rec
-    out = {
-        "metric": "sieved numbers/sec at 1 GPU (batched vs plain, bit-exact); p99 latency",
-        "value": main_rec["numbers_per_s"], "unit": "numbers/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_rec["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "%s: l=%d f=%d n=%d B=%d (u=%d, v=%d; 2^33 numbers centred at 1e12, plain sieve)"
-                   % (args.workload, main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"], u, v),
-                   "mode": "plain (one sieve_init per step, prime generation included)"},
-        "p50_ms": main_rec["p50_ms"], "p99_ms": main_rec["p99_ms"],
-        "ms_per_step_with_kernel_events": main_rec["ms_per_step_with_kernel_events"],
-        "bit_exact": main_rec.get("bit_exact"),
-        "roofline": roof,
-        "kernels_ms_per_step": {k: round(x["total_ms"], 4) for k, x in main_rec["kernels"].items()},
-        "also": {k: {kk: vv for kk, vv in r.items() if kk in ("numbers_per_s", "ms_per_step", "p50_ms", "p99_ms",
-                                                               "bit_exact", "B", "large_prime_hits")}
-                 | {"kernels_ms_per_step": {kk: round(x["total_ms"], 4) for kk, x in r["kernels"].items()}}
-                 for k, r in also.items()},
-    }
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    rates = None if args.no_unit_rates else unit_rates()
+    out = {"metric": "sieved numbers/sec at 1 GPU (batched vs plain, bit-exact); p99 latency", "unit": "numbers/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
     tune = None
-    if args.batch_steps > 0:
-        out["batch"] = run_batch_bench(args.batch_steps, log)
-        tune = out["batch"]["tune"]
+    if args.workload == "batch_1234":
+        log("batch: autotune and %d timed steps" % args.steps)
+        rec = run_batch(args.steps, args.warmup, log)
+        primes = rec.pop("_primes")
+        tune = rec["tune"]
+        marks, hits = batch_work(primes, rec["reqs"], tune)
+        ks = rec["kernels"]
+        dom = max(ks, key=lambda k: ks[k]["total_ms"])
+        kt = ks[dom]
+        per_ms = kt["total_ms"] / kt["launches_per_step"]
+        if dom == "k_bucket_scatter":
+            roof = roofline_hbm(dom, BUCKET_BYTES_PER_HIT * hits / kt["launches_per_step"], per_ms,
+                                traffic_from_profile("batch_1234", dom),
+                                "%d bytes per large-prime hit (%.4g hits per step)" % (BUCKET_BYTES_PER_HIT, hits))
+        else:
+            roof = roofline_lds(dom, marks / kt["launches_per_step"], per_ms, traffic_from_profile("batch_1234", dom),
+                                rates)
+        out.update({"value": rec["numbers_per_s"], "ms_per_step": rec["ms_per_step"],
+                    "config": {"workload": BATCH_WORKLOAD,
+                               "mode": "one sieve_batch of all 256 requests per step (tuned %s); the plain "
+                                       "per-interval kernel looped over the same requests beside it" % (tune,),
+                               "numbers_per_step": rec["numbers"]},
+                    "p50_ms": rec["p50_ms"], "p99_ms": rec["p99_ms"], "wall_ms_per_step": rec["wall_ms_per_step"],
+                    "bit_exact": rec["bit_exact"],
+                    "plain": {"loop_shared_table": rec["plain_loop_shared_table"],
+                              "loop_sieve_init": rec["plain_loop_sieve_init"],
+                              "batched_speedup_vs_loop": rec["speedup_vs_plain_loop"]},
+                    "roofline": roof, "autotune_s": rec["autotune_s"],
+                    "work_per_step": {"algorithmic_marks": marks, "large_prime_hits": hits},
+                    "kernels_ms_per_step": {k: round(x["total_ms"], 4) for k, x in ks.items()}})
+        headline_reqs = rec["reqs"]
+    else:
+        rec = run_plain(args.workload, args.steps, args.warmup)
+        roofs = plain_rooflines(rec, rates)
+        dom = rec["dominant_kernel"]
+        out.update({"value": rec["numbers_per_s"], "ms_per_step": rec["ms_per_step"],
+                    "config": {"workload": "%s: l=%d f=%d n=%d B=%d (u=%d, v=%d)" % (
+                        args.workload, rec["l"], rec["f"], rec["n"], rec["B"], rec["u"], rec["v"]),
+                        "mode": "plain (one sieve_init per step, prime generation included)"},
+                    "p50_ms": rec["p50_ms"], "p99_ms": rec["p99_ms"], "bit_exact": rec.get("bit_exact"),
+                    "roofline": roofs.get(dom) or next(iter(roofs.values()), None),
+                    "kernels_ms_per_step": {k: round(x["total_ms"], 4) for k, x in rec["kernels"].items()}})
+        headline_reqs = None
+    also, rooflines = {}, []
+    for name in [x for x in args.also.split(",") if x and x != "none" and x != args.workload]:
+        log("plain workload %s" % name)
+        r = run_plain(name, max(3, args.steps // 2), 2)
+        roofs = plain_rooflines(r, rates)
+        for k, ro in roofs.items():
+            rooflines.append(dict(ro, workload=name))
+        also[name] = {kk: r[kk] for kk in ("numbers_per_s", "ms_per_step", "p50_ms", "p99_ms", "bit_exact", "B",
+                                          "dominant_kernel")}
+        also[name]["kernels_ms_per_step"] = {kk: round(x["total_ms"], 4) for kk, x in r["kernels"].items()}
+    out["also"] = also
+    out["rooflines"] = rooflines
+    if args.latency_steps > 0:
+        log("latency: %d calls of the small interval" % args.latency_steps)
+        out["latency_small"] = run_latency(args.latency_steps)
     if args.serve_seconds > 0:
-        out["serving"] = run_serving_bench(args.serve_seconds, tune)
+        sps = [float(x) for x in args.serve_speedups.split(",") if x]
+        out["serving"] = run_serving(args.serve_seconds, sps, tune, log)
     if rates is not None:
         out["unit_rates"] = rates
+    out["host"] = host_info()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(main_rec["l"], main_rec["f"], main_rec["n"], main_rec["B"])
-        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(main_rec["l"], main_rec["f"], main_rec["n"],
-                                                               main_rec["B"])
+        log("cpu baseline")
+        if headline_reqs is not None:
+            cb = cpu_baseline_batch(headline_reqs)
+            out["cpu_baseline"] = cb
+            out["cpu_baseline_all_cores"] = cpu_baseline_batch_all_cores(headline_reqs, one_core_rate=cb["value"])
+        else:
+            out["cpu_baseline"] = cpu_baseline_plain(rec["l"], rec["f"], rec["n"], rec["B"])
     print(json.dumps(out), flush=True)
 
 

@@ -155,13 +155,29 @@ int sieve_ctx_sieve_with(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uin
  * same as sieve_init would give for it alone. */
 int sieve_batch(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
                 size_t nreq, const sieve_tune *tune, void *stream);
-/* Device scratch bytes sieve_batch needs for these requests (bucket storage and
- * per-request state; not counting the caller's S and counts), for admission
- * control.  The bucket part follows the hit count of Sections 2.2-2.3 (a prime p
- * hits a span of s bits about s/p times; summed over the large primes).  Pure host
- * computation. */
+/* --- device memory accounting (for admission control by a byte budget) ---
+ * sieve_batch_scratch_bytes: the device bytes a fresh context holds after
+ * sieve_batch on these requests (bucket storage and per-request state; not the
+ * caller's S and counts, not the prime table).  The bucket part follows the hit
+ * count of Sections 2.2-2.3 (a prime p hits a span of s bits about s/p times,
+ * summed over the large primes).  Computed by a planning pass of sieve_batch that
+ * allocates and enqueues nothing; it queries the current device's attributes.
+ * S_dev / counts_dev of reqs are not read and may be NULL.
+ * sieve_sieve_scratch_bytes: the same for sieve_ctx_sieve_with (pr given) or
+ * sieve_ctx_sieve (pr NULL: the context's own prime table up to B included).
+ * A context's buffers only grow, so a call on a used context adds at most these
+ * bytes to what sieve_ctx_scratch_bytes reports for it. */
 int sieve_batch_scratch_bytes(const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
                               size_t nreq, const sieve_tune *tune, uint64_t *bytes);
+int sieve_sieve_scratch_bytes(const sieve_primes *pr, uint32_t l, uint64_t f, uint64_t n,
+                              uint64_t B, const sieve_tune *tune, uint64_t *bytes);
+/* Device bytes the context's scratch buffers hold now. */
+int sieve_ctx_scratch_bytes(sieve_ctx *ctx, uint64_t *bytes);
+/* Synchronises the context's last stream and frees all its scratch buffers (the
+ * next call allocates again).  Clears the context's device error word. */
+int sieve_ctx_trim(sieve_ctx *ctx);
+/* Device bytes of a prime table. */
+int sieve_primes_bytes(const sieve_primes *pr, uint64_t *bytes);
 
 /* --- allocation-free one-shot entry point ---
  * For callers that cannot allocate device memory (code under HIP graph capture,

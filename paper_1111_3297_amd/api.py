@@ -126,6 +126,23 @@ class Context:
                 "sieve_batch_scratch_bytes")
         return out.value
 
+    def sieve_scratch_bytes(self, l, f, n, B, tune=None, primes=None):
+        """Device bytes a fresh context holds after sieve() of this request (planning pass)."""
+        out = ctypes.c_uint64()
+        L.check(L.load().sieve_sieve_scratch_bytes(primes.h if primes is not None else None, l, f, n, B, _tune(tune),
+                                                   ctypes.byref(out)), "sieve_sieve_scratch_bytes")
+        return out.value
+
+    def scratch_bytes(self):
+        """Device bytes this context's scratch buffers hold now."""
+        out = ctypes.c_uint64()
+        L.check(L.load().sieve_ctx_scratch_bytes(self.h, ctypes.byref(out)), "sieve_ctx_scratch_bytes")
+        return out.value
+
+    def trim(self):
+        """Free this context's scratch buffers (synchronises its last stream)."""
+        L.check(L.load().sieve_ctx_trim(self.h), "sieve_ctx_trim")
+
     def check_device_errors(self):
         L.check(L.load().sieve_check_device_errors(self.h), "sieve_check_device_errors")
 
@@ -157,6 +174,12 @@ class Primes:
         c, b = ctypes.c_uint64(), ctypes.c_uint64()
         L.check(L.load().sieve_primes_info(h, ctypes.byref(c), ctypes.byref(b)), "sieve_primes_info")
         self.count, self.bound = c.value, b.value
+
+    def nbytes(self):
+        """Device bytes of the table."""
+        out = ctypes.c_uint64()
+        L.check(L.load().sieve_primes_bytes(self.h, ctypes.byref(out)), "sieve_primes_bytes")
+        return out.value
 
     def to_tensor(self, stream=None):
         t = torch.empty(self.count, dtype=torch.int32, device="cuda")

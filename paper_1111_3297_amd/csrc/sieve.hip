@@ -18,6 +18,25 @@ namespace {
 
 thread_local int g_last_hip = 0;
 
+struct DevBuf;
+// Dry run: while set, DevBuf::ensure records the size it would grow to instead of
+// allocating, and no kernel, copy or event is enqueued (a pure host planning pass
+// that gives the exact device bytes of a call).
+struct DryRun {
+  std::vector<std::pair<const DevBuf*, size_t>> want;
+  void note(const DevBuf* b, size_t n) {
+    for (auto& w : want)
+      if (w.first == b) { w.second = std::max(w.second, n); return; }
+    want.emplace_back(b, n);
+  }
+};
+thread_local DryRun* g_dry = nullptr;
+// The stream of the call in progress on this thread: a growing buffer waits for
+// the work enqueued on it (the context's earlier calls are ordered before it)
+// before the old memory is released.
+thread_local hipStream_t g_call_stream = nullptr;
+thread_local bool g_in_call = false;
+
 #define HIPCHK(expr)                                   \
   do {                                                 \
     hipError_t e_ = (expr);                            \
@@ -47,11 +66,13 @@ struct DevBuf {
   size_t bytes = 0;
   bool fixed = false;
   int ensure(size_t n) {
+    if (g_dry) { g_dry->note(this, std::max<size_t>(n, 256)); return SIEVE_OK; }
     if (n <= bytes) return SIEVE_OK;
     if (fixed) return SIEVE_E_SCRATCH;
     if (p) {
-      // previous users on any stream must be done before the memory is released
-      hipError_t e = hipDeviceSynchronize();
+      // earlier users must be done before the memory is released: the kernels of
+      // this call and of the owner's earlier calls, all ordered on the call's stream
+      hipError_t e = g_in_call ? hipStreamSynchronize(g_call_stream) : hipDeviceSynchronize();
       if (e != hipSuccess) { g_last_hip = (int)e; return SIEVE_E_HIP; }
       (void)hipFree(p);
       p = nullptr;
@@ -177,16 +198,21 @@ struct sieve_ctx {
   struct Pending { std::string name; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::map<std::string, KernelTime> times;
+  // every device buffer the context owns
+  template <typename F>
+  void each_buf(F&& f) {
+    DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
+                      &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
+                      &own.P, &own.cnt, &xpat};
+    for (DevBuf* b : bufs) f(*b);
+    for (auto& b : pat) f(b);
+  }
   ~sieve_ctx();
 };
 
 sieve_ctx::~sieve_ctx() {
   if (has_last) (void)hipStreamSynchronize(last_stream);
-  DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
-                    &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
-                    &own.P, &own.cnt};
-  for (DevBuf* b : bufs) b->release();
-  for (auto& b : pat) b.release();
+  each_buf([](DevBuf& b) { b.release(); });
   for (auto& e : ev_pool) (void)hipEventDestroy(e);
   for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   if (done) (void)hipEventDestroy(done);
@@ -211,6 +237,7 @@ hipEvent_t take_event(sieve_ctx* c) {
 // Launch wrapper: records an event pair around the kernel when timing is on.
 template <typename F>
 int launch(sieve_ctx* c, const char* name, hipStream_t s, F&& f) {
+  if (g_dry) return SIEVE_OK;
   hipEvent_t a = nullptr, b = nullptr;
   if (c->timing) {
     a = take_event(c);
@@ -245,6 +272,7 @@ int collect_times(sieve_ctx* c) {
 // `total` bytes; upload copies a host table into it and enqueues the copy;
 // pin_end records the event that guards the next reuse.
 int pin_begin(sieve_ctx* c, size_t total) {
+  if (g_dry) return SIEVE_OK;
   if (c->pin_pending) {
     HIPCHK(hipEventSynchronize(c->pin_ev));
     c->pin_pending = false;
@@ -262,7 +290,7 @@ int pin_begin(sieve_ctx* c, size_t total) {
   return SIEVE_OK;
 }
 int upload(sieve_ctx* c, hipStream_t s, void* dst, const void* src, size_t n) {
-  if (!n) return SIEVE_OK;
+  if (!n || g_dry) return SIEVE_OK;
   if (c->pin_used + n > c->pin_bytes) return SIEVE_E_ARG;
   char* p = static_cast<char*>(c->pin) + c->pin_used;
   memcpy(p, src, n);
@@ -271,6 +299,7 @@ int upload(sieve_ctx* c, hipStream_t s, void* dst, const void* src, size_t n) {
   return SIEVE_OK;
 }
 int pin_end(sieve_ctx* c, hipStream_t s) {
+  if (g_dry) return SIEVE_OK;
   if (c->pin_used) {
     HIPCHK(hipEventRecord(c->pin_ev, s));
     c->pin_pending = true;
@@ -378,7 +407,7 @@ int get_pattern(sieve_ctx* c, uint64_t B, hipStream_t s, const uint32_t** pat, u
     STCHK(launch(c, "k_pattern", s, [&] {
       sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->pat[m].as<uint32_t>(), P, pp, nw);
     }));
-    c->pat_words[m] = nw;
+    if (!g_dry) c->pat_words[m] = nw;
   }
   *pat = c->pat[m].as<uint32_t>();
   *per = P;
@@ -404,7 +433,7 @@ int get_xpattern(sieve_ctx* c, hipStream_t s, const uint32_t** xpat) {
         sv::k_pattern<<<(nw + 255) / 256, 256, 0, s>>>(c->xpat.as<uint32_t>() + sv::kXOff[i], sv::kXPer[i], pp, nw);
       }));
     }
-    c->xpat_ready = true;
+    if (!g_dry) c->xpat_ready = true;
   }
   *xpat = c->xpat.as<uint32_t>();
   return SIEVE_OK;
@@ -444,6 +473,7 @@ void launch_tile(const sieve_ctx* c, uint32_t L, hipStream_t s, sv::TileArgs ta)
 int ensure_err(sieve_ctx* c, hipStream_t s) {
   if (c->err_ready) return SIEVE_OK;
   STCHK(c->err.ensure(64));
+  if (g_dry) return SIEVE_OK;
   sv::k_fill_u32<<<1, 64, 0, s>>>(c->err.as<uint32_t>(), 16, 0);
   HIPCHK(hipGetLastError());
   c->err_ready = true;
@@ -810,16 +840,37 @@ int begin(sieve_ctx* c, hipStream_t s) {
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     c->ncu = (uint32_t)std::max(ncu, 1);
   }
+  if (g_dry) return SIEVE_OK;
   STCHK(set_lds_limits());
   if (c->has_last && c->last_stream != s) HIPCHK(hipStreamWaitEvent(s, c->done, 0));
+  g_call_stream = s;
+  g_in_call = true;
   return SIEVE_OK;
 }
 
 int end(sieve_ctx* c, hipStream_t s) {
+  g_in_call = false;
+  if (g_dry) return SIEVE_OK;
   if (!c->done) HIPCHK(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
   HIPCHK(hipEventRecord(c->done, s));
   c->last_stream = s;
   c->has_last = true;
+  return SIEVE_OK;
+}
+
+// Runs fn on a fresh context in dry-run mode: the device bytes its buffers would
+// hold afterwards (nothing is allocated or enqueued).
+template <typename F>
+int dry_bytes(F&& fn, uint64_t* bytes) {
+  sieve_ctx tmp;
+  DryRun d;
+  g_dry = &d;
+  const int rc = fn(&tmp);
+  g_dry = nullptr;
+  if (rc != SIEVE_OK) return rc;
+  uint64_t tot = 0;
+  for (auto& w : d.want) tot += w.second;
+  *bytes = tot;
   return SIEVE_OK;
 }
 
@@ -1213,28 +1264,6 @@ void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::Batch
 #undef SV_TB
 }
 
-// Device scratch (bytes) of a batch with these windows: slabs of offsets,
-// bucket entries, histograms and the per-window tables.
-uint64_t batch_bytes(const std::vector<Window>& W, const Resolved& R, uint32_t l) {
-  const uint64_t med_lim = 1ull << R.Mlog;
-  const uint32_t esz = R.b <= 16 ? 2 : 4;
-  uint64_t qp = 0, off = 0, cap = 0, bins = 0, hg = 0, tiles = 0;
-  for (const Window& w : W) {
-    qp += pi_upper(std::min<uint64_t>(w.B, med_lim)) + 16;
-    off += pi_upper(w.B) + 16;
-    tiles += (w.lbits + (1u << R.L) - 1) >> R.L;
-    if (w.B >= med_lim) {
-      const uint64_t nb = (w.lbits + (1ull << R.b) - 1) >> R.b;
-      // at most 256 workgroups per request, each with a group-rounded region per bin
-      cap += window_cap(w, med_lim) + 256 * nb * (sv::kRegionBytes / esz - 1);
-      bins += nb;
-      hg += nb * 256;
-    }
-  }
-  (void)l;
-  return qp * 8 + off * 4 + cap * esz + bins * 12 + hg * 4 + tiles * 4 + W.size() * sizeof(sv::BatchReq) + 4096;
-}
-
 }  // namespace
 
 extern "C" {
@@ -1396,13 +1425,44 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
 int sieve_batch_scratch_bytes(const sieve_primes* pr, uint32_t l, const sieve_req* reqs, size_t nreq,
                               const sieve_tune* tune, uint64_t* bytes) {
   if (!pr || !bytes || (!reqs && nreq)) return SIEVE_E_ARG;
-  Resolved R;
-  STCHK(resolve_tune(l, tune, &R));
   std::vector<sieve_req> rr(reqs, reqs + nreq);
   for (auto& r : rr) { if (!r.S_dev) r.S_dev = reinterpret_cast<uint32_t*>(16); if (!r.counts_dev) r.counts_dev = reinterpret_cast<uint32_t*>(16); }
-  std::vector<Window> W;
-  STCHK(batch_windows(pr, l, rr.data(), nreq, R, &W));
-  *bytes = batch_bytes(W, R, l);
+  return dry_bytes([&](sieve_ctx* c) { return sieve_batch(c, pr, l, rr.data(), nreq, tune, nullptr); }, bytes);
+}
+
+int sieve_sieve_scratch_bytes(const sieve_primes* pr, uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                              const sieve_tune* tune, uint64_t* bytes) {
+  if (!bytes) return SIEVE_E_ARG;
+  uint32_t* dummy = reinterpret_cast<uint32_t*>(16);
+  return dry_bytes([&](sieve_ctx* c) {
+    return pr ? sieve_ctx_sieve_with(c, pr, l, f, n, B, dummy, dummy, tune, nullptr)
+              : sieve_ctx_sieve(c, l, f, n, B, dummy, dummy, tune, nullptr);
+  }, bytes);
+}
+
+int sieve_ctx_scratch_bytes(sieve_ctx* ctx, uint64_t* bytes) {
+  if (!ctx || !bytes) return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  uint64_t tot = 0;
+  ctx->each_buf([&](DevBuf& b) { if (!b.fixed) tot += b.bytes; });
+  *bytes = tot;
+  return SIEVE_OK;
+}
+
+int sieve_ctx_trim(sieve_ctx* ctx) {
+  if (!ctx) return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (ctx->has_last) HIPCHK(hipStreamSynchronize(ctx->last_stream));
+  ctx->each_buf([](DevBuf& b) { b.release(); });
+  for (auto& w : ctx->pat_words) w = 0;
+  ctx->xpat_ready = false;
+  ctx->err_ready = false;
+  return SIEVE_OK;
+}
+
+int sieve_primes_bytes(const sieve_primes* pr, uint64_t* bytes) {
+  if (!pr || !bytes) return SIEVE_E_ARG;
+  *bytes = pr->P.bytes + pr->cnt.bytes;
   return SIEVE_OK;
 }
 

@@ -3,7 +3,8 @@
 A request is an interval of Section 1.2.1 at segment size 2^l, (f, n), sieved with
 B = isqrt(v) (or a given bound).  The server replays an open-loop arrival
 schedule, admits waiting requests first come first served as long as an in-flight
-slot is free and the HBM budget (table + counts + batch scratch) allows, launches
+slot is free and the device memory budget allows (measured use plus an upper bound
+of what the group adds: table, counts and the library's planned scratch), launches
 each admitted group as one sieve_batch (a group of one as the plain per-interval
 call, which costs less) on that slot's own context and stream, and
 retires slots by polling their completion events.  Requests that arrive while
@@ -27,9 +28,11 @@ def request_bytes(l, n):
 
 
 class GpuExecutor:
-    """Runs groups of requests with sieve_batch, one context and stream per slot."""
+    """Runs groups of requests with sieve_batch (a group of one with the plain
+    per-interval call when single_plain, which has less fixed cost), one context
+    and stream per slot."""
 
-    def __init__(self, primes, l, slots=3, tune=None, keep_outputs=False):
+    def __init__(self, primes, l, slots=3, tune=None, keep_outputs=False, single_plain=True):
         import torch
         from . import api
         self.torch = torch
@@ -38,14 +41,53 @@ class GpuExecutor:
         self.l = l
         self.tune = tune
         self.keep = keep_outputs
+        self.single_plain = single_plain
         self.slots = [{"ctx": api.Context(), "stream": torch.cuda.Stream(), "busy": False} for _ in range(slots)]
+        self._cost = {}
+        torch.cuda.synchronize()
+        self._free0 = torch.cuda.mem_get_info()[0]   # free device memory before any request
 
     def free_slots(self):
         return sum(1 for s in self.slots if not s["busy"])
 
-    def scratch_bytes(self, reqs):
-        ctx = self.slots[0]["ctx"]
-        return ctx.batch_scratch_bytes(self.primes, self.l, [(r.f, r.n, r.B) for r in reqs], tune=self.tune)
+    def request_bytes(self, r):
+        """Upper bound of the device bytes admitting r can add: its table and counts
+        plus the scratch a fresh context would need for it (the planning pass of the
+        library, for the batched and, when used, the plain call)."""
+        key = (r.f, r.n, r.B)
+        c = self._cost.get(key)
+        if c is None:
+            ctx = self.slots[0]["ctx"]
+            sc = ctx.batch_scratch_bytes(self.primes, self.l, [(r.f, r.n, r.B)], tune=self.tune)
+            if self.single_plain:
+                sc = max(sc, ctx.sieve_scratch_bytes(self.l, r.f, r.n, r.B, tune=self.tune, primes=self.primes))
+            c = request_bytes(self.l, r.n) + sc
+            self._cost[key] = c
+        return c
+
+    def fixed_bytes(self):
+        """Device bytes held whatever is admitted: the shared prime table."""
+        return self.primes.nbytes()
+
+    def device_bytes(self):
+        """Device bytes in use now: the prime table plus what the device's free memory
+        has dropped by since the executor was made (the slot contexts' scratch and the
+        outputs of requests in flight, at the allocators' real granularity)."""
+        return self.primes.nbytes() + max(0, self._free0 - self.torch.cuda.mem_get_info()[0])
+
+    def trim_idle(self):
+        """Free the scratch of idle slots and PyTorch's cached blocks."""
+        for s in self.slots:
+            if not s["busy"]:
+                s["ctx"].trim()
+        self.torch.cuda.empty_cache()
+
+    def _launch(self, slot, outs):
+        if len(outs) == 1 and self.single_plain:
+            f, n, B, S, c = outs[0]
+            slot["ctx"].sieve(self.l, f, n, B, S, c, tune=self.tune, stream=slot["stream"], primes=self.primes)
+        else:
+            slot["ctx"].batch(self.primes, self.l, outs, tune=self.tune, stream=slot["stream"])
 
     def submit(self, reqs):
         torch = self.torch
@@ -56,13 +98,7 @@ class GpuExecutor:
             for r in reqs:
                 S, c = self.api.alloc(self.l, r.n)
                 outs.append((r.f, r.n, r.B, S, c))
-            if len(outs) == 1:
-                # a group of one (light load): the plain per-interval call has less
-                # fixed cost than a batch of one, with the same result
-                f, n, B, S, c = outs[0]
-                slot["ctx"].sieve(self.l, f, n, B, S, c, tune=self.tune, stream=slot["stream"], primes=self.primes)
-            else:
-                slot["ctx"].batch(self.primes, self.l, outs, tune=self.tune, stream=slot["stream"])
+            self._launch(slot, outs)
             host_counts = [torch.empty(r.n, dtype=torch.int32, pin_memory=True) for r in reqs]
             for hc, o in zip(host_counts, outs):
                 hc.copy_(o[4], non_blocking=True)
@@ -91,34 +127,34 @@ class PlainExecutor(GpuExecutor):
     time on one stream, shared prime table (the baseline for the batched server)."""
 
     def __init__(self, primes, l, tune=None, keep_outputs=False):
-        super().__init__(primes, l, slots=1, tune=tune, keep_outputs=keep_outputs)
+        super().__init__(primes, l, slots=1, tune=tune, keep_outputs=keep_outputs, single_plain=True)
 
-    def scratch_bytes(self, reqs):
-        return super().scratch_bytes(reqs)
+    def request_bytes(self, r):
+        key = (r.f, r.n, r.B)
+        c = self._cost.get(key)
+        if c is None:
+            ctx = self.slots[0]["ctx"]
+            c = request_bytes(self.l, r.n) + ctx.sieve_scratch_bytes(self.l, r.f, r.n, r.B, tune=self.tune,
+                                                                      primes=self.primes)
+            self._cost[key] = c
+        return c
 
-    def submit(self, reqs):
-        torch = self.torch
-        slot = self.slots[0]
-        slot["busy"] = True
-        with torch.cuda.stream(slot["stream"]):
-            outs, host_counts = [], []
-            for r in reqs:
-                S, c = self.api.alloc(self.l, r.n)
-                slot["ctx"].sieve(self.l, r.f, r.n, r.B, S, c, tune=self.tune, stream=slot["stream"],
-                                  primes=self.primes)
-                hc = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
-                hc.copy_(c, non_blocking=True)
-                outs.append((r.f, r.n, r.B, S, c))
-                host_counts.append(hc)
-            ev = torch.cuda.Event()
-            ev.record(slot["stream"])
-        return {"slot": slot, "reqs": reqs, "outs": outs, "host_counts": host_counts, "event": ev}
+    def _launch(self, slot, outs):
+        for f, n, B, S, c in outs:
+            slot["ctx"].sieve(self.l, f, n, B, S, c, tune=self.tune, stream=slot["stream"], primes=self.primes)
 
 
 class Server:
-    """Open-loop replay with HBM-budget admission and continuous batching."""
+    """Open-loop replay with device-memory budget admission and continuous batching.
 
-    def __init__(self, executor, l=20, budget_bytes=64 << 30, max_group=64, poll_s=20e-6, clock=None, sleep=None):
+    Admission measures the device memory in use (executor.device_bytes(): the prime
+    table, the slot contexts' scratch and PyTorch's allocator) and admits the next
+    waiting request into the group being formed while that, plus the upper bounds of
+    the group's requests (executor.request_bytes), stays within the budget.  A request
+    that does not fit while idle slots hold scratch frees that scratch first."""
+
+    def __init__(self, executor, l=20, budget_bytes=64 << 30, max_group=64, poll_s=20e-6, clock=None, sleep=None,
+                 progress=None, progress_s=10.0):
         self.ex = executor
         self.l = l
         self.budget = budget_bytes
@@ -126,44 +162,37 @@ class Server:
         self.poll_s = poll_s
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
+        self.progress = progress
+        self.progress_s = progress_s
         self.peak_bytes = 0
-        self._cost = {}
-
-    def cost_bytes(self, reqs):
-        """Budget charge of a group: outputs plus batch scratch, summed per request
-        (the scratch estimate is additive over requests)."""
-        tot = 0
-        for r in reqs:
-            c = self._cost.get(r.rid)
-            if c is None:
-                c = request_bytes(self.l, r.n) + self.ex.scratch_bytes([r])
-                self._cost[r.rid] = c
-            tot += c
-        return tot
+        self.trims = 0
 
     def run(self, requests):
         """requests: Requests sorted by arrival (seconds from start).  Returns
         (results by rid, stats)."""
         reqs = sorted(requests, key=lambda r: r.arrival)
+        fixed = self.ex.fixed_bytes()
         for r in reqs:
-            if self.cost_bytes([r]) > self.budget:
-                raise ValueError("request %s alone exceeds the HBM budget" % (r.rid,))
+            if fixed + self.ex.request_bytes(r) > self.budget:
+                raise ValueError("request %s alone exceeds the device memory budget" % (r.rid,))
         pending = collections.deque()
         inflight = []
-        used = 0
         results, lat = {}, {}
         i = 0
         t0 = self.clock()
-        first_launch = None
         last_done = 0.0
+        next_report = self.progress_s
         while i < len(reqs) or pending or inflight:
             now = self.clock() - t0
             while i < len(reqs) and reqs[i].arrival <= now:
                 pending.append(reqs[i])
                 i += 1
+            if self.progress and now >= next_report:
+                self.progress(now, len(results), len(reqs))
+                next_report += self.progress_s
             # retire finished groups
             still = []
-            for h, nbytes in inflight:
+            for h in inflight:
                 if self.ex.done(h):
                     out = self.ex.finish(h)
                     tdone = self.clock() - t0
@@ -171,27 +200,30 @@ class Server:
                     for r in h["reqs"]:
                         results[r.rid] = out[r.rid]
                         lat[r.rid] = tdone - r.arrival
-                    used -= nbytes
                 else:
-                    still.append((h, nbytes))
+                    still.append(h)
             inflight = still
             # admit: first come first served, as many as fit the budget
+            trimmed = False
             while pending and self.ex.free_slots() > 0:
+                used = self.ex.device_bytes()
                 group, gbytes = [], 0
                 while pending and len(group) < self.max_group:
-                    cb = self.cost_bytes([pending[0]])
+                    cb = self.ex.request_bytes(pending[0])
                     if used + gbytes + cb > self.budget:
                         break
                     group.append(pending.popleft())
                     gbytes += cb
                 if not group:
+                    if not trimmed:
+                        self.ex.trim_idle()
+                        self.trims += 1
+                        trimmed = True
+                        continue
                     break
                 h = self.ex.submit(group)
-                if first_launch is None:
-                    first_launch = self.clock() - t0
-                used += gbytes
-                self.peak_bytes = max(self.peak_bytes, used)
-                inflight.append((h, gbytes))
+                self.peak_bytes = max(self.peak_bytes, self.ex.device_bytes())
+                inflight.append(h)
             if not inflight and not pending and i < len(reqs):
                 wait = reqs[i].arrival - (self.clock() - t0)
                 if wait > 0:
@@ -210,13 +242,14 @@ class Server:
         stats = {"requests": len(reqs), "numbers": numbers, "span_s": span,
                  "numbers_per_s": numbers / span, "p50_ms": 1e3 * pct(0.50), "p99_ms": 1e3 * pct(0.99),
                  "max_ms": 1e3 * (ls[-1] if ls else float("nan")), "peak_bytes": self.peak_bytes,
-                 "budget_bytes": self.budget}
+                 "budget_bytes": self.budget, "trims": self.trims}
         return results, stats
 
 
-def serving_requests(l=20, seed=99, rate=200.0, seconds=60.0, limit_s=None):
+def serving_requests(l=20, seed=99, rate=200.0, seconds=60.0, limit_s=None, speedup=1.0):
     """The seeded Poisson stream of paper_1111_3297_amd.workloads as Requests with
-    B = isqrt(v); limit_s keeps only arrivals before that time."""
+    B = isqrt(v); limit_s keeps only arrivals before that time (of the original
+    stream); speedup divides every arrival time (the same requests offered faster)."""
     from . import workloads
     out = []
     for k, (t, f21, n21, kind) in enumerate(workloads.serving_stream(seed, rate, seconds)):
@@ -224,5 +257,5 @@ def serving_requests(l=20, seed=99, rate=200.0, seconds=60.0, limit_s=None):
             break
         f, n = f21 << (20 - l), n21 << (20 - l)
         u, v = workloads.interval(l, f, n)
-        out.append(Request(k, t, f, n, math.isqrt(v)))
+        out.append(Request(k, t / speedup, f, n, math.isqrt(v)))
     return out

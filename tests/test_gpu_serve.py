@@ -64,3 +64,38 @@ def test_plain_fcfs_server_matches_batched():
     for r in reqs:
         assert np.array_equal(a[r.rid]["counts"], b[r.rid]["counts"]), r
         assert torch.equal(a[r.rid]["S"], b[r.rid]["S"]), r
+
+
+def test_admission_keeps_device_memory_within_a_binding_budget():
+    # a budget that binds: the prime table, the slot contexts' scratch and the
+    # outputs in flight never exceed it (measured by the device's free memory), and
+    # the results stay the oracle's
+    import torch
+    from paper_1111_3297_amd import api, serve
+    g = _serve_golden()
+    l = 20
+    reqs = serve.serving_requests(l=l, limit_s=0.45, speedup=20.0)
+    pr = api.Primes(max(r.B for r in reqs))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    ex = serve.GpuExecutor(pr, l, slots=3, keep_outputs=False)
+    big = max(ex.request_bytes(r) for r in reqs)
+    budget = pr.nbytes() + 2 * big
+    say("budget", budget, "largest request bound", big)
+    seen = []
+    submit = ex.submit
+
+    def watched(group):
+        h = submit(group)
+        seen.append(free0 - torch.cuda.mem_get_info()[0] + pr.nbytes())
+        return h
+    ex.submit = watched
+    res, st = serve.Server(ex, l=l, budget_bytes=budget).run(reqs)
+    say("stats", st, "measured peak", max(seen))
+    assert st["peak_bytes"] <= budget
+    assert max(seen) <= budget
+    for r in reqs:
+        c = res[r.rid]["counts"]
+        assert [int(c.astype(np.int64).sum()), hashlib.sha256(c.astype("<u4").tobytes()).hexdigest()[:16]] == \
+            g["requests"][r.rid][:2], r

@@ -23,29 +23,53 @@ class FakeClock:
 
 
 class FakeExecutor:
-    """Completes a group `service_s` seconds of virtual time after submission."""
+    """Completes a group `service_s` seconds of virtual time after submission.  Each
+    slot keeps the scratch of its largest group (as a library context keeps its
+    grown buffers) until trim_idle frees it; device_bytes is that plus the outputs
+    and scratch of the groups in flight."""
 
     def __init__(self, clock, l, slots=2, service_s=0.01, scratch=1000):
         self.clock, self.l, self.nslots, self.service_s, self.scratch = clock, l, slots, service_s, scratch
-        self.busy = 0
         self.order = []
+        self.retained = [0] * slots
+        self.busy = [None] * slots
+        self.trims = 0
 
     def free_slots(self):
-        return self.nslots - self.busy
+        return sum(1 for b in self.busy if b is None)
 
-    def scratch_bytes(self, reqs):
-        return self.scratch * len(reqs)
+    def request_bytes(self, r):
+        return serve.request_bytes(self.l, r.n) + self.scratch
+
+    def fixed_bytes(self):
+        return 0
+
+    def device_bytes(self):
+        out = sum(self.retained)
+        for b in self.busy:
+            if b is not None:
+                out += sum(serve.request_bytes(self.l, r.n) for r in b["reqs"])
+        return out
+
+    def trim_idle(self):
+        self.trims += 1
+        for k, b in enumerate(self.busy):
+            if b is None:
+                self.retained[k] = 0
 
     def submit(self, reqs):
-        self.busy += 1
+        k = self.busy.index(None)
+        h = {"reqs": reqs, "t_done": self.clock.now() + self.service_s, "slot": k}
+        self.busy[k] = h
+        self.retained[k] = max(self.retained[k], self.scratch * len(reqs))
         self.order.extend(r.rid for r in reqs)
-        return {"reqs": reqs, "t_done": self.clock.now() + self.service_s}
+        return h
 
     def done(self, h):
         return self.clock.now() >= h["t_done"]
 
     def finish(self, h):
-        self.busy -= 1
+        self.busy[h["slot"]] = None
         out = {}
         for r in h["reqs"]:
             _, c = O.sieve(self.l, r.f, r.n, r.B)
@@ -82,16 +106,28 @@ def test_all_requests_served_with_oracle_counts_in_arrival_order():
 
 
 def test_budget_is_never_exceeded():
+    # retained scratch of idle slots counts against the budget and is freed when a
+    # waiting request would not fit otherwise
     clock = FakeClock()
     l = 10
     ex = FakeExecutor(clock, l, slots=8, service_s=0.05, scratch=4000)
     per = serve.request_bytes(l, 3) + 4000
     budget = 5 * per
+    seen = []
+    orig = ex.device_bytes
+
+    def spy():
+        v = orig()
+        seen.append(v)
+        return v
+    ex.device_bytes = spy
     srv = serve.Server(ex, l=l, budget_bytes=budget, clock=clock.now, sleep=clock.sleep)
     reqs = make_requests(l, 40, rate=2000.0, seed=5)
     res, st = srv.run(reqs)
     assert len(res) == 40
     assert st["peak_bytes"] <= budget
+    assert max(seen) <= budget
+    assert ex.trims > 0
 
 
 def test_request_larger_than_budget_is_rejected():
