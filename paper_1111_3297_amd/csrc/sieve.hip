@@ -54,7 +54,7 @@ thread_local bool g_in_call = false;
 
 constexpr uint64_t kLaunchBits = sv::kWinBits;  // offsets of one launch window fit 32 bits
 constexpr uint32_t kGenTile = 20;             // largest tile of the prime generator
-constexpr uint32_t kBatchRun = 4;             // consecutive tiles per batch work item
+constexpr uint32_t kBatchRun = 4;             // most consecutive tiles per batch work item
 constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or more use two bin ranges by default
 constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
 constexpr uint32_t kMaxCountBins = 32768;      // bins of one count job (its LDS histogram: 128 KB)
@@ -1246,10 +1246,10 @@ uint64_t window_cap(const Window& w, uint64_t med_lim) {
 
 template <typename E>
 void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::BatchReq* rq, uint32_t nreq, uint32_t nitems,
-                       uint32_t* queue, const uint32_t* P, const uint32_t* xpat, const void* bucket,
+                       uint32_t run, uint32_t* queue, const uint32_t* P, const uint32_t* xpat, const void* bucket,
                        const uint32_t* bstart, uint32_t b, uint32_t cap, uint32_t l, uint32_t* tcnt) {
 #define SV_TB(LL)                                                                                                  \
-  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, kBatchRun, queue, P, xpat, bucket, bstart, b, cap, \
+  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, run, queue, P, xpat, bucket, bstart, b, cap, \
                                                 l, tcnt)
   switch (L) {
     case 13: SV_TB(13); break;
@@ -1291,13 +1291,20 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   uint32_t items = 0, gbins = 0, tcnt = 0, seg_tot = 0, max_rbins = 1;
   const uint32_t* xpat = nullptr;
   const bool seg_long = L < l;
+  // tiles per work item: runs of kBatchRun carry offsets from tile to tile, but a
+  // batch with few tiles per resident workgroup takes shorter runs, so that its
+  // tiles spread over the device instead of queueing behind each other
+  uint64_t all_tiles = 0;
+  for (const Window& X : W) all_tiles += (X.lbits + (1ull << L) - 1) >> L;
+  const uint64_t resident = (uint64_t)c->ncu * tiles_per_cu(L);
+  const uint32_t run = all_tiles >= 4 * resident ? kBatchRun : (all_tiles >= 2 * resident ? 2u : 1u);
   for (uint32_t w = 0; w < nw; ++w) {
     const Window& X = W[w];
     sv::BatchReq& q = c->h_req[w];
     memset(&q, 0, sizeof q);
     q.G0 = X.G0; q.B = X.B; q.lbits = X.lbits;
     q.ntiles = (X.lbits + (1u << L) - 1) >> L;
-    q.item0 = items; items += (q.ntiles + kBatchRun - 1) / kBatchRun;
+    q.item0 = items; items += (q.ntiles + run - 1) / run;
     q.psq = (uint32_t)std::min<uint64_t>(isqrt_u64(2 * X.G0 + 1), 0xFFFFFFFFull);
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, X.B, s, &pat, &per, &patw, &pmask));
@@ -1315,7 +1322,7 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     if (seg_long) tcnt += q.ntiles;
     c->h_seg0[w] = seg_tot;
     seg_tot += X.lbits >> l;
-    for (uint32_t k = 0; k * 256u < q.off_cap; ++k) c->h_blk.push_back(make_uint2(w, k));
+    for (uint32_t k = 0; k * 256u * sv::kOffPer < q.off_cap; ++k) c->h_blk.push_back(make_uint2(w, k));
     if (X.B >= med_lim) {
       q.nbins = (X.lbits + (1u << b) - 1) >> b;
       q.bin_base = gbins;
@@ -1338,7 +1345,8 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   for (uint32_t w = 0; w < nw; ++w) {
     const sv::BatchReq& q = c->h_req[w];
     if (!q.nbins) continue;
-    const uint32_t groups = (uint32_t)std::min<double>(256.0, std::max<double>(1.0, std::round((double)R.groups * 2 * work[w] / work_tot)));
+    const uint32_t groups = (uint32_t)std::min<double>((double)R.groups,
+                                                       std::max<double>(1.0, std::round((double)R.groups * 2 * work[w] / work_tot)));
     const size_t jb = c->h_jobs.size();
     chunk_jobs(q.nbins, q.lbits, b, R.R, groups, (double)med_lim, (double)q.B, pr->P.as<uint32_t>(),
                reinterpret_cast<const sv::Plan*>((uintptr_t)w), reinterpret_cast<const uint32_t*>((uintptr_t)w), nullptr,
@@ -1407,12 +1415,12 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   const uint32_t* bsp = njobs ? c->bstart.as<uint32_t>() : nullptr;
   if (esz == 2)
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
+      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, run, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
                                   b, cap32, l, tc);
     }));
   else
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
+      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, run, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
                                   b, cap32, l, tc);
     }));
   if (seg_long)

@@ -65,6 +65,15 @@ class GpuExecutor:
             self._cost[key] = c
         return c
 
+    def request_cost_ms(self, r):
+        """Rough device time of r alone (a fit of measured plain calls on this device):
+        launch overhead, tiles, and for bounds in the bucket range the per-prime work of
+        the offsets and the bucket fill, which dominates heavy requests."""
+        cost = 0.03 + 2e-4 * (r.n << self.l >> 20)
+        if r.B >= (1 << 20):
+            cost += 0.1 + 1.0e-8 * r.B / math.log(r.B)
+        return cost
+
     def fixed_bytes(self):
         """Device bytes held whatever is admitted: the shared prime table."""
         return self.primes.nbytes()
@@ -150,15 +159,19 @@ class Server:
     Admission measures the device memory in use (executor.device_bytes(): the prime
     table, the slot contexts' scratch and PyTorch's allocator) and admits the next
     waiting request into the group being formed while that, plus the upper bounds of
-    the group's requests (executor.request_bytes), stays within the budget.  A request
-    that does not fit while idle slots hold scratch frees that scratch first."""
+    the group's requests (executor.request_bytes), stays within the budget and the
+    group's estimated device time (executor.request_cost_ms) within group_ms, or
+    within the waiting work's share per free slot when that is larger (a request
+    heavier than the cap forms a group of its own).  A request that does not
+    fit while idle slots hold scratch frees that scratch first."""
 
-    def __init__(self, executor, l=20, budget_bytes=64 << 30, max_group=64, poll_s=20e-6, clock=None, sleep=None,
-                 progress=None, progress_s=10.0):
+    def __init__(self, executor, l=20, budget_bytes=64 << 30, max_group=64, group_ms=0.5, poll_s=20e-6, clock=None,
+                 sleep=None, progress=None, progress_s=10.0):
         self.ex = executor
         self.l = l
         self.budget = budget_bytes
         self.max_group = max_group
+        self.group_ms = group_ms
         self.poll_s = poll_s
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
@@ -207,13 +220,23 @@ class Server:
             trimmed = False
             while pending and self.ex.free_slots() > 0:
                 used = self.ex.device_bytes()
-                group, gbytes = [], 0
+                # under a backlog the free slots share the waiting work, so groups
+                # grow with it (batching pays most when the device is saturated)
+                cap_ms = max(self.group_ms, sum(self.ex.request_cost_ms(r) for r in pending)
+                             / max(1, self.ex.free_slots()))
+                group, gbytes, gms = [], 0, 0.0
                 while pending and len(group) < self.max_group:
                     cb = self.ex.request_bytes(pending[0])
+                    cm = self.ex.request_cost_ms(pending[0])
                     if used + gbytes + cb > self.budget:
+                        break
+                    # a group holds about group_ms of device work, so that light
+                    # requests do not wait behind a heavy one of the same group
+                    if group and gms + cm > cap_ms:
                         break
                     group.append(pending.popleft())
                     gbytes += cb
+                    gms += cm
                 if not group:
                     if not trimmed:
                         self.ex.trim_idle()

@@ -44,6 +44,9 @@ class FakeExecutor:
     def fixed_bytes(self):
         return 0
 
+    def request_cost_ms(self, r):
+        return 0.0
+
     def device_bytes(self):
         out = sum(self.retained)
         for b in self.busy:
