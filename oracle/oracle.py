@@ -42,6 +42,9 @@ def _load():
         lib.oracle_sieve_with.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                           u32p, ctypes.c_long, u32p, u32p]
         lib.oracle_sieve_with.restype = ctypes.c_int
+        lib.oracle_goldbach.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint64,
+                                        u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p]
+        lib.oracle_goldbach.restype = ctypes.c_int
         lib.oracle_odd_primes.argtypes = [ctypes.c_uint64, ctypes.POINTER(u32p)]
         lib.oracle_odd_primes.restype = ctypes.c_long
         lib.oracle_lemma1_offset.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
@@ -90,6 +93,26 @@ def sieve_with(l, f, n, B, P):
     if rc != 0:
         raise OracleError("oracle_sieve_with(l=%d, f=%d, n=%d, B=%d) -> %d" % (l, f, n, B, rc))
     return S[:nwords], c[:n]
+
+
+def goldbach(l, f, n, S, Q, per_number=True):
+    """Goldbach check of the even numbers u+1 .. v against the table S of (l, f, n)
+    and the odd primes q <= Q (see oracle_goldbach in sieve_oracle.c): returns
+    (minq per even number or None, maxq, argk, fails per segment)."""
+    lib = _load()
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    S = np.ascontiguousarray(S, dtype=np.uint32)
+    assert S.size >= (n << l) // 32
+    minq = np.zeros(n << l, dtype=np.uint32) if per_number else None
+    maxq = np.zeros(n, dtype=np.uint32)
+    argk = np.zeros(n, dtype=np.uint64)
+    fails = np.zeros(n, dtype=np.uint32)
+    rc = lib.oracle_goldbach(l, f, n, S.ctypes.data_as(u32p), Q,
+                             minq.ctypes.data_as(u32p) if per_number else None, maxq.ctypes.data_as(u32p),
+                             argk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), fails.ctypes.data_as(u32p))
+    if rc != 0:
+        raise OracleError("oracle_goldbach(l=%d, f=%d, n=%d, Q=%d) -> %d" % (l, f, n, Q, rc))
+    return minq, maxq, argk, fails
 
 
 def odd_primes(B):

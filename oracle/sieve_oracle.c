@@ -163,3 +163,47 @@ long long oracle_count_total(uint32_t l, uint64_t f, uint64_t n, uint64_t B)
     free(S); free(c);
     return rc == 0 ? tot : -1;
 }
+
+/* Goldbach verification over a sieve table (Section 5: the program was written to
+ * verify the Goldbach conjecture, and the prime table is the bulk of that work).
+ * The table S is that of (l, f, n): bit j stands for the odd number u + 2j, zero
+ * when it has no odd prime factor up to the table's bound (a prime, when the bound
+ * reaches isqrt(v)).  The even numbers N_k = u + 1 + 2k, k = 0 .. n*2^l - 1, are
+ * checked against the odd primes q <= Q in ascending order: N_k - q = u + 2(k - d)
+ * with d = (q - 1)/2, which lies in the table when d <= k.
+ *   minq[k]  = the least such q with d <= k and bit k - d of S zero; 0 if none;
+ * and per segment t (k in [t*2^l, (t+1)*2^l)):
+ *   maxq[t]  = the largest nonzero minq[k] of the segment (0 if every one is 0),
+ *   argk[t]  = the least k of the segment with minq[k] == maxq[t] (k of the
+ *              segment's first even number when maxq[t] == 0),
+ *   fails[t] = the number of k of the segment with minq[k] == 0.
+ * minq may be NULL.  Parity status: pinned (tests/test_oracle_pins.py: trial
+ * division and Miller-Rabin on the numbers N - q themselves). */
+int oracle_goldbach(uint32_t l, uint64_t f, uint64_t n, const uint32_t *S, uint64_t Q,
+                    uint32_t *minq, uint32_t *maxq, uint64_t *argk, uint32_t *fails)
+{
+    uint64_t F, NB, u, v;
+    int rc = oracle_interval(l, f, n, 3, &F, &NB, &u, &v);
+    if (rc) return rc;
+    if (Q < 3 || Q >= ((uint64_t)1 << 32)) return OR_E_BOUND;
+    uint32_t *P = NULL;
+    long np = oracle_odd_primes(Q, &P);
+    if (np < 0) return OR_E_NOMEM;
+    uint64_t seg = (uint64_t)1 << l;
+    for (uint64_t t = 0; t < n; ++t) { maxq[t] = 0; argk[t] = t * seg; fails[t] = 0; }
+    for (uint64_t k = 0; k < NB; ++k) {
+        uint32_t best = 0;
+        for (long i = 0; i < np; ++i) {
+            uint64_t d = (P[i] - 1) / 2;
+            if (d > k) break;                          /* N_k - q below u: not in the table */
+            uint64_t j = k - d;
+            if (((S[j >> 5] >> (j & 31)) & 1u) == 0) { best = P[i]; break; }
+        }
+        if (minq) minq[k] = best;
+        uint64_t t = k >> l;
+        if (best == 0) fails[t] += 1;
+        else if (best > maxq[t]) { maxq[t] = best; argk[t] = k; }
+    }
+    free(P);
+    return OR_OK;
+}

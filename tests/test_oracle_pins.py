@@ -236,3 +236,84 @@ def test_prime_table_goldens_match_published_pi():
     # independent cross-check value
     g2 = json.load(open(os.path.join(HERE, "golden", "primes_2133783848.json")))
     assert g2["count"] == 104459685 and g2["count"] + 1 <= pub[2147483648]
+
+
+def test_goldbach_records_match_published_table():
+    # the table of 1 .. 2^22 (primes <= 2048): the running maxima of the least q
+    # over the even numbers are the published Goldbach records
+    S, _ = O.sieve(15, 0, 64, 2048)
+    minq, maxq, argk, fails = O.goldbach(15, 0, 64, S, 2048)
+    want = []
+    with open(os.path.join(HERE, "golden", "goldbach_records.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].split()
+            if line:
+                want.append((int(line[0]), int(line[1])))
+    rec, best = [], 0
+    for k in np.flatnonzero(minq):
+        if minq[k] > best:
+            best = int(minq[k])
+            rec.append((2 + 2 * int(k), best))
+    assert rec == want
+    # only N = 2 and N = 4 (= 2 + 2, the odd primes cannot reach it) fail
+    assert int(fails.sum()) == 2 and list(np.flatnonzero(minq == 0)) == [0, 1]
+
+
+def _least_q_brute(N, k, Q, prime):
+    q = 3
+    while q <= Q and (q - 1) // 2 <= k:
+        if prime(q) and prime(N - q):
+            return q
+        q += 2
+    return 0
+
+
+def test_goldbach_against_trial_division():
+    rng = random.Random(11)
+    for _ in range(8):
+        l = rng.choice([5, 7, 9, 10])
+        n = rng.randint(1, 6)
+        f = rng.choice([0, rng.randint(0, 3000)])
+        u, v = O.interval(l, f, n)
+        S, _ = O.sieve(l, f, n, max(3, math.isqrt(v)))
+        Q = rng.choice([3, 17, 200, 1000])
+        minq, maxq, argk, fails = O.goldbach(l, f, n, S, Q)
+        prime = lambda x: x >= 2 and smallest_odd_factor(x) == x if x % 2 else x == 2
+        for k in range(n << l):
+            assert minq[k] == _least_q_brute(u + 1 + 2 * k, k, Q, prime), (l, f, n, Q, k)
+        # the per-segment summary follows from the per-number values
+        seg = 1 << l
+        for t in range(n):
+            m = minq[t * seg:(t + 1) * seg]
+            assert fails[t] == int((m == 0).sum())
+            assert maxq[t] == int(m.max())
+            if maxq[t]:
+                assert argk[t] == t * seg + int(np.flatnonzero(m == maxq[t])[0])
+
+
+def test_goldbach_partial_table_and_large_numbers():
+    # a partial table (B < isqrt(v)): the check reads "no odd prime factor <= B"
+    l, f, n, B = 8, 7000, 3, 31
+    u, v = O.interval(l, f, n)
+    S, _ = O.sieve(l, f, n, B)
+    minq, _, _, _ = O.goldbach(l, f, n, S, 500)
+    rough = lambda x: all(x % p for p in range(3, B + 1, 2) if smallest_odd_factor(p) == p and p < x)
+    for k in range(n << l):
+        N = u + 1 + 2 * k
+        q = 3
+        want = 0
+        while q <= 500 and (q - 1) // 2 <= k:
+            if smallest_odd_factor(q) == q and rough(N - q):
+                want = q
+                break
+            q += 2
+        assert minq[k] == want, k
+    # near 10^12 with the full bound: sampled even numbers by Miller-Rabin
+    l, f, n = 12, (10**12) >> 13, 4
+    u, v = O.interval(l, f, n)
+    S, _ = O.sieve(l, f, n, math.isqrt(v))
+    minq, _, _, fails = O.goldbach(l, f, n, S, 5000)
+    rng = random.Random(3)
+    for k in rng.sample(range(3000, n << l), 300):
+        assert minq[k] == _least_q_brute(u + 1 + 2 * k, k, 5000, is_prime_mr), k
+    assert int(fails[1:].sum()) == 0
