@@ -179,6 +179,30 @@ int sieve_ctx_trim(sieve_ctx *ctx);
 /* Device bytes of a prime table. */
 int sieve_primes_bytes(const sieve_primes *pr, uint64_t *bytes);
 
+/* --- Goldbach check over a sieve table (Section 5: the verification the program
+ * was written for, for which the prime table is the bulk of the work) ---
+ * S_dev is the table of (l, f, n) as sieve_init writes it (n*2^l/32 words; a zero
+ * bit stands for an odd number with no odd prime factor up to the table's bound,
+ * i.e. a prime when the bound reached isqrt(v)).  The even numbers
+ * N_k = u + 1 + 2k, k = 0 .. n*2^l - 1, are checked against the odd primes
+ * q <= Q of the table pr (Q <= its bound), ascending: N_k - q is table bit k - d
+ * with d = (q - 1)/2, available when d <= k.
+ *   minq[k]  (optional, minq_dev may be NULL; n*2^l uint32) = the least such q
+ *            whose bit is zero, 0 if none;
+ * per segment t (the numbers k in [t*2^l, (t+1)*2^l)), n entries each:
+ *   maxq_dev[t]  = the largest nonzero minq of the segment (0 if none),
+ *   argk_dev[t]  = the least k of the segment with that minq (t*2^l if maxq is 0),
+ *   fails_dev[t] = the numbers of the segment with minq 0 (N - q < u for every q
+ *                  that works, or no q <= Q works: a counterexample candidate
+ *                  up to Q when d_max <= k).
+ * All outputs are caller-owned device memory, written on stream.  The context's
+ * scratch holds one 8-byte maximum per segment.  Errors: SIEVE_E_ARG (null
+ * pointers, l, n, more than 2^44 table bits), SIEVE_E_RANGE, SIEVE_E_BOUND (Q < 3 or
+ * Q above the prime table's bound). */
+int sieve_goldbach(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t f, uint64_t n,
+                   const uint32_t *S_dev, uint64_t Q, uint32_t *maxq_dev, uint64_t *argk_dev,
+                   uint32_t *fails_dev, uint32_t *minq_dev, void *stream);
+
 /* --- allocation-free one-shot entry point ---
  * For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  Same arguments, result

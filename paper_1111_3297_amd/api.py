@@ -126,6 +126,23 @@ class Context:
                 "sieve_batch_scratch_bytes")
         return out.value
 
+    def goldbach(self, primes, l, f, n, S, Q, per_number=False, stream=None):
+        """Goldbach check of the even numbers of the table S of (l, f, n) against the
+        odd primes q <= Q (include/sieve.h: sieve_goldbach).  Returns CUDA tensors
+        (maxq int32[n], argk int64[n], fails int32[n], minq int32[n*2^l] or None),
+        enqueued on the stream."""
+        _require_cuda_i32(S, (n << l) // 32, "S")
+        maxq = torch.empty(n, dtype=torch.int32, device=S.device)
+        argk = torch.empty(n, dtype=torch.int64, device=S.device)
+        fails = torch.empty(n, dtype=torch.int32, device=S.device)
+        minq = torch.empty(n << l, dtype=torch.int32, device=S.device) if per_number else None
+        L.check(L.load().sieve_goldbach(self.h, primes.h, l, f, n, ctypes.c_void_p(S.data_ptr()), Q,
+                                        ctypes.c_void_p(maxq.data_ptr()), ctypes.c_void_p(argk.data_ptr()),
+                                        ctypes.c_void_p(fails.data_ptr()),
+                                        ctypes.c_void_p(minq.data_ptr()) if per_number else None, _stream(stream)),
+                "sieve_goldbach")
+        return maxq, argk, fails, minq
+
     def sieve_scratch_bytes(self, l, f, n, B, tune=None, primes=None):
         """Device bytes a fresh context holds after sieve() of this request (planning pass)."""
         out = ctypes.c_uint64()

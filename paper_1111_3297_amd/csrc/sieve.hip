@@ -177,6 +177,7 @@ struct sieve_ctx {
   DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk, mb_sink;
   // batch scratch and the host copies of its tables
   DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, cjobs, cblk2job, thr;
+  DevBuf gb_best, gb_k;   // Goldbach check: packed per-segment maxima, prime count
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk;
   std::vector<uint32_t> h_seg0;
@@ -203,7 +204,7 @@ struct sieve_ctx {
   void each_buf(F&& f) {
     DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
                       &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
-                      &own.P, &own.cnt, &xpat};
+                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k};
     for (DevBuf* b : bufs) f(*b);
     for (auto& b : pat) f(b);
   }
@@ -1576,5 +1577,44 @@ extern "C" int sieve_init_noalloc(uint32_t l, uint64_t f, uint64_t n, uint64_t B
   STCHK(begin(c, s));
   STCHK(build_primes(c, B, &c->own, s));
   STCHK(run_sieve(c, &c->own, l, F, NB, B, S_dev, counts_dev, R, s));
+  return end(c, s);
+}
+
+extern "C" int sieve_goldbach(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, uint64_t f, uint64_t n,
+                              const uint32_t* S_dev, uint64_t Q, uint32_t* maxq_dev, uint64_t* argk_dev,
+                              uint32_t* fails_dev, uint32_t* minq_dev, void* stream) {
+  if (!ctx || !pr || !S_dev || !maxq_dev || !argk_dev || !fails_dev) return SIEVE_E_ARG;
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, 3, &F, &NB));
+  if (Q < 3 || Q > pr->B) return SIEVE_E_BOUND;
+  if ((NB / 32 + 255) / 256 > 0x7FFFFFFFull) return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  sieve_ctx* c = ctx;
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(c, s));
+  STCHK(c->gb_best.ensure((size_t)n * 8 + 64));
+  STCHK(c->gb_k.ensure(64));
+  unsigned long long* best = c->gb_best.as<unsigned long long>();
+  const uint32_t fill_blocks = (uint32_t)std::min<uint64_t>((2 * n + 255) / 256, 4096);
+  STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<fill_blocks, 256, 0, s>>>(c->gb_best.as<uint32_t>(), 2 * n, 0); }));
+  STCHK(launch(c, "k_fill_u32", s, [&] {
+    sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(fails_dev, n, 0);
+  }));
+  if (minq_dev)
+    STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<4096, 256, 0, s>>>(minq_dev, NB, 0); }));
+  STCHK(launch(c, "k_gb_count", s, [&] {
+    sv::k_gb_count<<<1, 1, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), Q, c->gb_k.as<uint32_t>());
+  }));
+  sv::GbArgs a;
+  a.S = S_dev; a.nwords = NB / 32; a.P = pr->P.as<uint32_t>(); a.K = c->gb_k.as<uint32_t>(); a.l = l;
+  a.best = best; a.fails = fails_dev; a.minq = minq_dev;
+  const uint64_t grid = (a.nwords + 255) / 256;
+  STCHK(launch(c, "k_goldbach", s, [&] {
+    if (minq_dev) sv::k_goldbach<true><<<(uint32_t)grid, 256, 0, s>>>(a);
+    else sv::k_goldbach<false><<<(uint32_t)grid, 256, 0, s>>>(a);
+  }));
+  STCHK(launch(c, "k_gb_finish", s, [&] {
+    sv::k_gb_finish<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(best, n, l, maxq_dev, argk_dev);
+  }));
   return end(c, s);
 }
