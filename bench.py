@@ -476,6 +476,55 @@ def run_serving(seconds, speedups, tune, log, slots=3):
     return out
 
 
+def run_goldbach(steps, Q=1 << 16):
+    """The Goldbach check of every even number of the 1e12 table (2^32 numbers,
+    u+1 .. v) against the odd primes q <= Q: the table from sieve_init (checked against
+    the oracle's golden), then sieve_goldbach timed alone; two segments recomputed by
+    the oracle."""
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api, workloads
+    l, f, n, B = workloads.plain_configs()["interval_1e12"]
+    S, c = api.alloc(l, n)
+    api.sieve_init(l, f, n, B, S, c)
+    ctx = api.Context()
+    pr = api.Primes(max(B, Q))
+    torch.cuda.synchronize()
+    g = _golden("interval_1e12")
+    table_ok = g is not None and hashlib.sha256(S.cpu().numpy().tobytes()).hexdigest() == g["S_sha256"]
+    stream = torch.cuda.current_stream()
+    outs = {}
+
+    def call():
+        outs["r"] = ctx.goldbach(pr, l, f, n, S, Q)
+    for _ in range(3):
+        call()
+    lat, _ = _step_times(call, steps, stream)
+    kernels = _kernel_times(ctx, call, max(2, steps // 2))
+    maxq, argk, fails, _ = outs["r"]
+    mh, ah, fh = maxq.cpu().numpy().view(np.uint32), argk.cpu().numpy().view(np.uint64), fails.cpu().numpy()
+    from oracle import oracle as O
+    ok = True
+    for t in (1, n - 1):
+        So, _ = O.sieve(l, f + t - 1, 2, B)
+        _, mx, ak, fl = O.goldbach(l, f + t - 1, 2, So, Q, per_number=False)
+        ok = ok and (int(mh[t]), int(ah[t]), int(fh[t])) == (int(mx[1]), int(ak[1]) + ((t - 1) << l), int(fl[1]))
+    kt = kernels["k_goldbach"]
+    per_ms = kt["total_ms"] / kt["launches_per_step"]
+    nb = (n << l) // 8 + 16 * n
+    u, v = workloads.interval(l, f, n)
+    best = int(np.argmax(mh))
+    return {"workload": "Goldbach check of the even numbers %d .. %d (2^32 numbers) against the table of "
+                        "interval_1e12 and the odd primes q <= %d" % (u + 1, v, Q),
+            "ms_per_call": sum(lat) / len(lat), "p99_ms": _pct(lat, 0.99),
+            "even_numbers_per_s": (n << l) / (sum(lat) / len(lat) * 1e-3),
+            "largest_least_q": int(mh[best]), "at_N": int(u + 1 + 2 * int(ah[best])), "failures": int(fh.sum()),
+            "table_bit_exact": table_ok, "sampled_segments_bit_exact": ok,
+            "kernels_ms_per_call": {k: round(x["total_ms"], 4) for k, x in kernels.items()},
+            "roofline": roofline_hbm("k_goldbach", nb, per_ms, traffic_from_profile("goldbach_1e12", "k_goldbach"),
+                                     "the table read once (%d bytes) and 16 bytes of output per segment" % ((n << l) // 8))}
+
+
 def unit_rates():
     """Measured unit rates the roofline figures are set against: the library's LDS-atomic, VALU
     and 64-bit remainder microbenchmarks (sieve_microbench, median of three) and its plain HBM
@@ -544,6 +593,7 @@ def main():
     ap.add_argument("--workload", default="batch_1234", help="batch_1234 (headline) or a plain interval workload")
     ap.add_argument("--also", default="interval_1e12,interval_2p60", help="comma list of plain workloads to report")
     ap.add_argument("--latency-steps", type=int, default=200, help="calls of the small interval for launch latency")
+    ap.add_argument("--goldbach-steps", type=int, default=10, help="timed Goldbach checks of the 1e12 table (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="seconds of the request stream to replay (0: skip)")
     ap.add_argument("--serve-speedups", default="10,30,100", help="time-compressed replays of the same stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -635,6 +685,10 @@ def main():
         also[name] = {kk: r[kk] for kk in ("numbers_per_s", "ms_per_step", "p50_ms", "p99_ms", "bit_exact", "B",
                                           "dominant_kernel")}
         also[name]["kernels_ms_per_step"] = {kk: round(x["total_ms"], 4) for kk, x in r["kernels"].items()}
+    if args.goldbach_steps > 0:
+        log("goldbach check")
+        out["goldbach"] = run_goldbach(args.goldbach_steps)
+        rooflines.append(dict(out["goldbach"]["roofline"], workload="goldbach_1e12"))
     out["also"] = also
     out["rooflines"] = rooflines
     if args.latency_steps > 0:
