@@ -34,6 +34,8 @@ CUS, CLOCK_HZ = 256, 2.4e9
 LDS_PEAK_OPS = CUS * CLOCK_HZ * 32          # one 32-bit access per LDS bank per clock, 32 banks per CU
 HBM_PEAK = 8.0e12                           # bytes/s, published HBM3E peak
 BUCKET_BYTES_PER_HIT = 8                    # the method's bucket entry (prime, offset), written once per hit
+VALU_LANE_OPS = CUS * CLOCK_HZ * 64         # one wave64 32-bit VALU instruction per clock per CU
+GB_TEST_PEAK = 32 * VALU_LANE_OPS           # Goldbach tests: 32 even numbers per 32-bit AND
 
 
 def marks_algorithmic(primes, u, v):
@@ -505,10 +507,15 @@ def run_goldbach(steps, Q=1 << 16):
     mh, ah, fh = maxq.cpu().numpy().view(np.uint32), argk.cpu().numpy().view(np.uint64), fails.cpu().numpy()
     from oracle import oracle as O
     ok = True
+    idx = []
+    Ptab = O.odd_primes(Q)
     for t in (1, n - 1):
         So, _ = O.sieve(l, f + t - 1, 2, B)
-        _, mx, ak, fl = O.goldbach(l, f + t - 1, 2, So, Q, per_number=False)
+        mq, mx, ak, fl = O.goldbach(l, f + t - 1, 2, So, Q)
         ok = ok and (int(mh[t]), int(ah[t]), int(fh[t])) == (int(mx[1]), int(ak[1]) + ((t - 1) << l), int(fl[1]))
+        seg = mq[1 << l:]
+        idx.append(float((np.searchsorted(Ptab, seg[seg > 0]) + 1).mean()))
+    tests = float(np.mean(idx)) * (n << l)
     kt = kernels["k_goldbach"]
     per_ms = kt["total_ms"] / kt["launches_per_step"]
     nb = (n << l) // 8 + 16 * n
@@ -522,7 +529,14 @@ def run_goldbach(steps, Q=1 << 16):
             "table_bit_exact": table_ok, "sampled_segments_bit_exact": ok,
             "kernels_ms_per_call": {k: round(x["total_ms"], 4) for k, x in kernels.items()},
             "roofline": roofline_hbm("k_goldbach", nb, per_ms, traffic_from_profile("goldbach_1e12", "k_goldbach"),
-                                     "the table read once (%d bytes) and 16 bytes of output per segment" % ((n << l) // 8))}
+                                     "the table read once (%d bytes) and 16 bytes of output per segment" % ((n << l) // 8)),
+            "roofline_alu": {"bound": "alu", "kernel": "k_goldbach", "unit": "Gtests/s",
+                             "achieved": tests / (per_ms * 1e-3) / 1e9, "peak": GB_TEST_PEAK / 1e9,
+                             "frac": tests / (per_ms * 1e-3) / GB_TEST_PEAK,
+                             "per_launch": {"tests": tests, "avg_ms": per_ms,
+                                            "what": "(number, prime) tests in ascending q up to each number's least q "
+                                                    "(mean index %.2f from two oracle segments), 32 per 32-bit lane "
+                                                    "operation at the peak" % float(np.mean(idx))}}}
 
 
 def unit_rates():

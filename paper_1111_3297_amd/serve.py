@@ -189,6 +189,7 @@ class Server:
             if fixed + self.ex.request_bytes(r) > self.budget:
                 raise ValueError("request %s alone exceeds the device memory budget" % (r.rid,))
         pending = collections.deque()
+        pending_ms = 0.0            # estimated device time of the waiting requests
         inflight = []
         results, lat = {}, {}
         i = 0
@@ -199,6 +200,7 @@ class Server:
             now = self.clock() - t0
             while i < len(reqs) and reqs[i].arrival <= now:
                 pending.append(reqs[i])
+                pending_ms += self.ex.request_cost_ms(reqs[i])
                 i += 1
             if self.progress and now >= next_report:
                 self.progress(now, len(results), len(reqs))
@@ -222,8 +224,7 @@ class Server:
                 used = self.ex.device_bytes()
                 # under a backlog the free slots share the waiting work, so groups
                 # grow with it (batching pays most when the device is saturated)
-                cap_ms = max(self.group_ms, sum(self.ex.request_cost_ms(r) for r in pending)
-                             / max(1, self.ex.free_slots()))
+                cap_ms = max(self.group_ms, pending_ms / max(1, self.ex.free_slots()))
                 group, gbytes, gms = [], 0, 0.0
                 while pending and len(group) < self.max_group:
                     cb = self.ex.request_bytes(pending[0])
@@ -237,6 +238,7 @@ class Server:
                     group.append(pending.popleft())
                     gbytes += cb
                     gms += cm
+                    pending_ms -= cm
                 if not group:
                     if not trimmed:
                         self.ex.trim_idle()

@@ -51,9 +51,10 @@ def test_goldbach_records_to_2_22():
 @pytest.mark.parametrize("case", [
     (5, 0, 40, 100, 97),            # one word per segment: per-lane atomics, failures near the start
     (7, 3, 50, 1000, 1000),
-    (12, 0, 9, 4096, 727),          # exactly the 128 register-resident primes
-    (12, 5, 9, 4096, 719),          # 127 primes: the general loop only
-    (12, 11, 9, 4096, 733),         # 129 primes: one from the table
+    (12, 0, 9, 4096, 1621),         # exactly the 256 register-resident primes
+    (12, 5, 9, 4096, 1619),         # 255 primes: the general loop only
+    (12, 11, 9, 4096, 1627),        # 257 primes: one from the table
+    (12, 3, 9, 4096, 727),
     (13, (10**9) >> 14, 5, 0, 13),  # Q = 13: failures everywhere; workgroup reduction
     (14, (10**9) >> 15, 3, 0, 40000),
     (16, (10**12) >> 17, 8, 0, 1 << 16),
