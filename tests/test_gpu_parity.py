@@ -119,6 +119,9 @@ def test_multi_chunk_and_bucket_path():
     # 32-bit bucket entries: one bin per tile
     check_case(17, (10**14) >> 18, 1 << 6, 3 * 10**6,
                tune={"tile_log2": 17, "medium_log2": 14, "bins_log2": 8, "bin_log2": 17, "groups": 80})
+    # eight bin ranges of one bin each
+    check_case(15, (10**13) >> 16, 8, 10**6, tune={"tile_log2": 15, "medium_log2": 11, "bins_log2": 8, "groups": 64,
+                                                     "ranges": 8})
 
 
 @pytest.mark.parametrize("case", [
