@@ -45,6 +45,9 @@ def _load():
         lib.oracle_goldbach.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u32p, ctypes.c_uint64,
                                         u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p]
         lib.oracle_goldbach.restype = ctypes.c_int
+        lib.oracle_logsieve.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint32, u32p, u32p, ctypes.POINTER(ctypes.c_uint8)]
+        lib.oracle_logsieve.restype = ctypes.c_int
         lib.oracle_odd_primes.argtypes = [ctypes.c_uint64, ctypes.POINTER(u32p)]
         lib.oracle_odd_primes.restype = ctypes.c_long
         lib.oracle_lemma1_offset.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
@@ -113,6 +116,23 @@ def goldbach(l, f, n, S, Q, per_number=True):
     if rc != 0:
         raise OracleError("oracle_goldbach(l=%d, f=%d, n=%d, Q=%d) -> %d" % (l, f, n, Q, rc))
     return minq, maxq, argk, fails
+
+
+def logsieve(l, f, n, B, T, with_sums=True):
+    """Log-add sieve of the odd numbers of (l, f, n) by the odd primes p <= B
+    (oracle_logsieve): returns (C bit table as uint32 words, counts of ones per
+    segment, the byte sums A or None)."""
+    lib = _load()
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    nb = n << l
+    C = np.zeros(max(nb // 32, 1), dtype=np.uint32)
+    c = np.zeros(max(n, 1), dtype=np.uint32)
+    A = np.zeros(nb, dtype=np.uint8) if with_sums else None
+    rc = lib.oracle_logsieve(l, f, n, B, T, C.ctypes.data_as(u32p), c.ctypes.data_as(u32p),
+                             A.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if with_sums else None)
+    if rc != 0:
+        raise OracleError("oracle_logsieve(l=%d, f=%d, n=%d, B=%d, T=%d) -> %d" % (l, f, n, B, T, rc))
+    return C[:nb // 32], c[:n], A
 
 
 def odd_primes(B):

@@ -207,3 +207,51 @@ int oracle_goldbach(uint32_t l, uint64_t f, uint64_t n, const uint32_t *S, uint6
     free(P);
     return OR_OK;
 }
+
+/* Log-add sieve over the same interval (Section 5: circles and buckets serve a
+ * wider range of sieving algorithms; a quadratic or number field sieve adds the
+ * logarithm of every factor-base prime at the positions it divides instead of
+ * setting a bit).  Here the factor base is the odd primes p <= B and the values
+ * are the odd numbers of the interval: position j (the number N = u + 2j) collects
+ *   A[j] = sum of floor(log2 p) over the odd primes p <= B that divide N
+ * (every odd multiple m*p with m >= 1, so a prime p <= B in the interval counts
+ * itself; each prime once whatever its power).  A[j] <= log2 N < 64, one byte.
+ *   C bit j = 1 iff A[j] >= T (a smoothness candidate), same bit layout as S;
+ *   counts[t] = the ones of C in segment t.
+ * A may be NULL.  Parity status: pinned (tests/test_oracle_pins.py: the sums by
+ * trial division, and the smooth numbers of small ranges by full factorisation). */
+int oracle_logsieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B, uint32_t T,
+                    uint32_t *C, uint32_t *counts, uint8_t *A)
+{
+    uint64_t F, NB, u, v;
+    int rc = oracle_interval(l, f, n, B, &F, &NB, &u, &v);
+    if (rc) return rc;
+    uint8_t *acc = (uint8_t *)calloc((size_t)NB, 1);
+    if (!acc) return OR_E_NOMEM;
+    uint32_t *P = NULL;
+    long np = oracle_odd_primes(B, &P);
+    if (np < 0) { free(acc); return OR_E_NOMEM; }
+    for (long i = 0; i < np; ++i) {
+        uint64_t p = P[i];
+        uint32_t w = 0;
+        while ((p >> (w + 1)) != 0) ++w;            /* floor(log2 p) */
+        u128 m = ((u128)u + p - 1) / p;              /* smallest m with m*p >= u */
+        if ((m & 1) == 0) m += 1;                    /* odd multiples only */
+        u128 N = m * p;
+        if (N > v) continue;
+        for (uint64_t j = (uint64_t)((N - u) / 2); j < NB; j += p) acc[j] = (uint8_t)(acc[j] + w);
+    }
+    free(P);
+    memset(C, 0, (size_t)(NB / 32) * 4);
+    for (uint64_t j = 0; j < NB; ++j)
+        if (acc[j] >= T) C[j >> 5] |= 1u << (j & 31);
+    uint64_t wps = ((uint64_t)1 << l) / 32;
+    for (uint64_t t = 0; t < n; ++t) {
+        uint64_t ones = 0;
+        for (uint64_t w = t * wps; w < (t + 1) * wps; ++w) ones += (uint64_t)__builtin_popcount(C[w]);
+        counts[t] = (uint32_t)ones;
+    }
+    if (A) memcpy(A, acc, (size_t)NB);
+    free(acc);
+    return OR_OK;
+}

@@ -317,3 +317,58 @@ def test_goldbach_partial_table_and_large_numbers():
     for k in rng.sample(range(3000, n << l), 300):
         assert minq[k] == _least_q_brute(u + 1 + 2 * k, k, 5000, is_prime_mr), k
     assert int(fails[1:].sum()) == 0
+
+
+def _odd_prime_factors(N):
+    out, d = [], 3
+    while N % 2 == 0:
+        N //= 2
+    while d * d <= N:
+        if N % d == 0:
+            out.append(d)
+            while N % d == 0:
+                N //= d
+        d += 2
+    if N > 1:
+        out.append(N)
+    return out
+
+
+def test_logsieve_sums_by_trial_division():
+    rng = random.Random(17)
+    for _ in range(10):
+        l = rng.choice([5, 6, 8, 10])
+        n = rng.randint(1, 5)
+        f = rng.choice([0, rng.randint(0, 5000), rng.randint(10**6, 10**7)])
+        u, v = O.interval(l, f, n)
+        B = rng.choice([3, 13, 97, 1000, max(3, math.isqrt(v))])
+        T = rng.randint(0, 40)
+        C, c, A = O.logsieve(l, f, n, B, T)
+        for j in range(n << l):
+            N = u + 2 * j
+            want = sum(p.bit_length() - 1 for p in _odd_prime_factors(N) if p <= B)
+            assert A[j] == want, (l, f, n, B, N)
+            assert ((int(C[j >> 5]) >> (j & 31)) & 1) == (want >= T)
+        assert [int(x) for x in c] == [int(sum(bin(int(w)).count("1") for w in C[t << (l - 5):(t + 1) << (l - 5)]))
+                                       for t in range(n)]
+
+
+def test_logsieve_smooth_numbers():
+    # with T = 0 every bit is one; with B >= N a prime counts its own floor(log2);
+    # an odd squarefree N whose prime factors are all <= B has A(N) >= log2 N minus
+    # its number of prime factors (each floor loses less than one)
+    l, f, n = 10, 0, 4
+    u, v = O.interval(l, f, n)
+    C, c, A = O.logsieve(l, f, n, v, 0)
+    assert int(c.sum()) == n << l
+    for j in range(1, n << l):
+        N = u + 2 * j
+        fs = _odd_prime_factors(N)
+        if len(fs) == 1 and fs[0] == N:
+            assert A[j] == N.bit_length() - 1
+        prod = 1
+        for p in fs:
+            prod *= p
+        if prod == N:
+            assert A[j] >= math.log2(N) - len(fs)
+    assert A[0] == 0    # the number 1
