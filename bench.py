@@ -215,11 +215,11 @@ def cpu_baseline_plain(l, f, n, B, budget_s=12.0):
                       % (ns, n, numbers, dt), "zero_bits": tot}
 
 
-def roofline_lds(kernel, marks_per_launch, per_launch_ms, traffic, rates=None, executed=None):
+def roofline_lds(kernel, marks_per_launch, per_launch_ms, traffic, rates=None, executed=None, what="marks"):
     achieved = marks_per_launch / (per_launch_ms * 1e-3)
     out = {"bound": "lds", "kernel": kernel, "achieved": achieved / 1e9, "peak": LDS_PEAK_OPS / 1e9,
-           "unit": "Gmarks/s", "frac": achieved / LDS_PEAK_OPS, "traffic": traffic,
-           "per_launch": {"algorithmic_marks": marks_per_launch, "avg_ms": per_launch_ms}}
+           "unit": "G%s/s" % what, "frac": achieved / LDS_PEAK_OPS, "traffic": traffic,
+           "per_launch": {"algorithmic_" + what: marks_per_launch, "avg_ms": per_launch_ms}}
     if rates is not None:
         # against the measured conflict-free LDS atomic rate, and the executed atomics
         # (wheel and masks leave about half the marks out) against the random-address rate
@@ -539,6 +539,59 @@ def run_goldbach(steps, Q=1 << 16):
                                                     "operation at the peak" % float(np.mean(idx))}}}
 
 
+def log_adds(primes, u, v):
+    """Additions the log-add sieve must make: every odd multiple m p (m >= 1) of every
+    odd prime p of the factor base in [u, v]."""
+    import numpy as np
+    p = primes.astype(np.int64)
+    hi = (int(v) // p + 1) // 2            # odd multiples <= v
+    lo = ((int(u) - 1) // p + 1) // 2      # odd multiples <= u - 1
+    return float((hi - lo).sum())
+
+
+def run_logsieve(steps, B=1 << 20, T=34):
+    """The log-add sieve of the 1e12 interval (2^32 odd numbers) with the odd primes
+    up to B as factor base and threshold T: candidates table and counts, timed per
+    call; two segments recomputed by the oracle."""
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api, workloads
+    l, f, n, _ = workloads.plain_configs()["interval_1e12"]
+    u, v = workloads.interval(l, f, n)
+    C, c = api.alloc(l, n)
+    ctx = api.Context()
+    pr = api.Primes(B)
+    stream = torch.cuda.current_stream()
+    call = lambda: ctx.logsieve(l, f, n, B, T, C, c, primes=pr)
+    for _ in range(2):
+        call()
+    lat, _ = _step_times(call, steps, stream)
+    kernels = _kernel_times(ctx, call, max(2, steps // 2))
+    ctx.check_device_errors()
+    Ch, ch = C.cpu().numpy().view(np.uint32), c.cpu().numpy().view(np.uint32)
+    from oracle import oracle as O
+    ok = True
+    w = 1 << (l - 5)
+    for t in (0, n - 1):
+        Co, co, _ = O.logsieve(l, f + t, 1, B, T, with_sums=False)
+        ok = ok and bool(np.array_equal(Ch[t * w:(t + 1) * w], Co)) and int(ch[t]) == int(co[0])
+    primes = pr.to_tensor().cpu().numpy().view(np.uint32)
+    torch.cuda.synchronize()
+    adds = log_adds(primes, u, v)
+    kt = kernels["k_logtile"]
+    per_ms = kt["total_ms"] / kt["launches_per_step"]
+    ms = sum(lat) / len(lat)
+    return {"workload": "log-add sieve of the odd numbers %d .. %d (2^32 positions) by the odd primes <= %d, "
+                        "threshold %d" % (u, v, B, T),
+            "ms_per_call": ms, "p99_ms": _pct(lat, 0.99), "numbers_per_s": (v - u + 1) / (ms * 1e-3),
+            "candidates": int(ch.astype(np.int64).sum()), "sampled_segments_bit_exact": ok,
+            "kernels_ms_per_call": {k: round(x["total_ms"], 4) for k, x in kernels.items()},
+            "roofline": dict(roofline_lds("k_logtile", adds / kt["launches_per_step"], per_ms,
+                                          traffic_from_profile("logsieve_1e12", "k_logtile"), what="adds"),
+                             note="an LDS add of floor(log2 p) at every odd multiple of every factor-base prime "
+                                  "(%.4g per call)" % adds)}
+
+
 def unit_rates():
     """Measured unit rates the roofline figures are set against: the library's LDS-atomic, VALU
     and 64-bit remainder microbenchmarks (sieve_microbench, median of three) and its plain HBM
@@ -608,6 +661,7 @@ def main():
     ap.add_argument("--also", default="interval_1e12,interval_2p60", help="comma list of plain workloads to report")
     ap.add_argument("--latency-steps", type=int, default=200, help="calls of the small interval for launch latency")
     ap.add_argument("--goldbach-steps", type=int, default=10, help="timed Goldbach checks of the 1e12 table (0: skip)")
+    ap.add_argument("--logsieve-steps", type=int, default=10, help="timed log-add sieves of the 1e12 interval (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="seconds of the request stream to replay (0: skip)")
     ap.add_argument("--serve-speedups", default="10,30,100", help="time-compressed replays of the same stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -703,6 +757,10 @@ def main():
         log("goldbach check")
         out["goldbach"] = run_goldbach(args.goldbach_steps)
         rooflines.append(dict(out["goldbach"]["roofline"], workload="goldbach_1e12"))
+    if args.logsieve_steps > 0:
+        log("log-add sieve")
+        out["logsieve"] = run_logsieve(args.logsieve_steps)
+        rooflines.append(dict(out["logsieve"]["roofline"], workload="logsieve_1e12"))
     out["also"] = also
     out["rooflines"] = rooflines
     if args.latency_steps > 0:

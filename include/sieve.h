@@ -203,6 +203,27 @@ int sieve_goldbach(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t 
                    const uint32_t *S_dev, uint64_t Q, uint32_t *maxq_dev, uint64_t *argk_dev,
                    uint32_t *fails_dev, uint32_t *minq_dev, void *stream);
 
+/* --- log-add sieve over the interval (Section 5: circles and buckets for a wider
+ * range of sieving algorithms, where a quadratic or number field sieve adds the
+ * logarithm of each factor-base prime at the positions it divides) ---
+ * Positions are the odd numbers N = u + 2j of the interval (l, f, n); the factor
+ * base is the odd primes p <= B (the table pr, or the context's own table up to B
+ * when pr is NULL); each adds floor(log2 p) at every odd multiple m*p, m >= 1 (each
+ * prime once, whatever its power).  A sum is at most log2 N < 64.
+ *   C_dev      (n*2^l/32 uint32 words, bit layout of S): bit j = 1 iff the sum at
+ *              u + 2j is at least T (0 <= T <= 255), a smoothness candidate;
+ *   counts_dev (n uint32): the ones of C per segment;
+ *   A_dev      (optional, NULL or n*2^l bytes): the sums themselves.
+ * Tiles of 2^tile_log2 positions (14..17, default 16; tune may be NULL) hold their
+ * byte sums in LDS; primes below the tile size are walked per tile, larger ones go
+ * through the buckets of Sections 2.2-2.5 with their weight in the entry (groups
+ * and ranges of the tune apply to that fill; the other fields are ignored).
+ * Errors as sieve_ctx_sieve, SIEVE_E_ARG also for T > 255 or a tile size out of
+ * range; bucket overflow sets the device error word. */
+int sieve_logsieve(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t f, uint64_t n,
+                   uint64_t B, uint32_t T, uint32_t *C_dev, uint32_t *counts_dev, uint8_t *A_dev,
+                   const sieve_tune *tune, void *stream);
+
 /* --- allocation-free one-shot entry point ---
  * For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  Same arguments, result

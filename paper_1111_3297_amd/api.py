@@ -143,6 +143,20 @@ class Context:
                 "sieve_goldbach")
         return maxq, argk, fails, minq
 
+    def logsieve(self, l, f, n, B, T, C, counts, A=None, primes=None, tune=None, stream=None):
+        """Log-add sieve of the odd numbers of (l, f, n) by the odd primes p <= B
+        (include/sieve.h: sieve_logsieve): C (int32 words) gets the candidates with
+        sum >= T, counts their number per segment, A (uint8[n*2^l], optional) the sums."""
+        _require_cuda_i32(C, (n << l) // 32, "C")
+        _require_cuda_i32(counts, n, "counts")
+        if A is not None and not (isinstance(A, torch.Tensor) and A.is_cuda and A.dtype == torch.uint8
+                                  and A.is_contiguous() and A.numel() >= (n << l)):
+            raise TypeError("A must be a contiguous uint8 CUDA tensor of n*2^l bytes")
+        L.check(L.load().sieve_logsieve(self.h, primes.h if primes is not None else None, l, f, n, B, T,
+                                        ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                                        ctypes.c_void_p(A.data_ptr()) if A is not None else None, _tune(tune),
+                                        _stream(stream)), "sieve_logsieve")
+
     def sieve_scratch_bytes(self, l, f, n, B, tune=None, primes=None):
         """Device bytes a fresh context holds after sieve() of this request (planning pass)."""
         out = ctypes.c_uint64()

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "sieve.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "kernels.inc"), os.path.join(ROOT, "include", "sieve.h")]
+DEPS = [SRC, os.path.join(HERE, "csrc", "kernels.inc"), os.path.join(HERE, "csrc", "logsieve.inc"),
+        os.path.join(ROOT, "include", "sieve.h")]
 LIB = os.path.join(HERE, "libsieve.so")
 
 HIPCC_FLAGS = [

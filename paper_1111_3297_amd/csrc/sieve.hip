@@ -13,6 +13,7 @@
 
 #include "sieve.h"
 #include "kernels.inc"
+#include "logsieve.inc"
 
 namespace {
 
@@ -383,7 +384,7 @@ int set_lds_limits() {
     // 8 KB); the scatter's stages and counters use at most 152 KB
     const int lim = kScatterLds;
     const void* fns[] = {(const void*)sv::k_bucket_count2, (const void*)sv::k_bucket_scatter2<uint16_t>,
-                         (const void*)sv::k_bucket_scatter2<uint32_t>};
+                         (const void*)sv::k_bucket_scatter2<uint32_t>, (const void*)sv::k_bucket_scatter2<uint32_t, true>};
     for (const void* f : fns)
       if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) rc = SIEVE_E_HIP;
   });
@@ -559,7 +560,7 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
                 const uint32_t* Ptab, const sv::Plan* plan, const uint32_t* OFF_in, uint32_t* OFF_out,
                 uint32_t gbin_base, std::vector<sv::BucketJob>* jobs, std::vector<uint32_t>* blk2job,
                 std::vector<sv::BucketJob>* cjobs, std::vector<uint32_t>* cblk2job,
-                std::vector<uint32_t>* thr, uint64_t* hg) {
+                std::vector<uint32_t>* thr, uint64_t* hg, uint32_t esz = 0) {
   // bin ranges: as given, or by default two for large chunks (a scatter workgroup
   // with fewer bins leaves fewer partly written lines in L2) and one otherwise; at
   // least enough for the LDS stages
@@ -577,8 +578,9 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
   thr->resize(t0 + GR);
   work_thresholds(lo_p, B, (double)rbins * (double)(1ull << b), GR, thr->data() + t0);
   // largest useful stage: about half a region's expected hits (larger stages would
-  // not fill before the last flush)
-  const uint32_t esz = b <= 16 ? 2 : 4;
+  // not fill before the last flush); entries of 16 bits for bins up to 2^16 bits
+  // unless 32-bit entries are asked for
+  if (!esz) esz = b <= 16 ? 2 : 4;
   const double exp_region = recip_sum_upper(lo_p, B) * std::ldexp(1.0, (int)b) / GR;
   uint32_t sbl_cap = 0;
   while ((2u << sbl_cap) * esz <= sv::kMaxStageBytes && (double)(2u << sbl_cap) <= exp_region / 2) ++sbl_cap;
@@ -592,6 +594,7 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
     C.thr = reinterpret_cast<const uint32_t*>((uintptr_t)t0);
     C.cbits = cbits; C.b = b; C.kb0 = 0; C.rbins = nbins; C.GR = GR;
     C.block0 = (uint32_t)cblk2job->size(); C.hg = hg0; C.hstride = nbins; C.gbin0 = gbin_base; C.sbl = 1;
+    C.esz = esz;
     for (uint32_t q = 0; q < GR; ++q) cblk2job->push_back((uint32_t)cjobs->size());
     cjobs->push_back(C);
     *hg += (uint64_t)GR * nbins;
@@ -606,6 +609,7 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
     J.cbits = cbits; J.b = b; J.rbins = std::min(rbins, nbins - J.kb0); J.update = (x + 1 == R) || (J.kb0 + rbins >= nbins);
     J.GR = GR; J.block0 = (uint32_t)blk2job->size(); J.hg = hg0 + J.kb0; J.hstride = nbins; J.gbin0 = gbin_base + J.kb0;
     J.sbl = sbl_cap;   // an upper bound here; set_stages fits it to the launch's LDS
+    J.esz = esz;
     for (uint32_t q = 0; q < GR; ++q) blk2job->push_back((uint32_t)jobs->size());
     jobs->push_back(J);
     if (J.update) break;
@@ -616,7 +620,7 @@ void chunk_jobs(uint32_t nbins, uint32_t cbits, uint32_t b, uint32_t ranges, uin
 // per-workgroup counts, scan over (bin, workgroup), staged scatter.
 int bucket_fill_jobs(sieve_ctx* c, const sv::BucketJob* djobs, const uint32_t* dblk2job, uint32_t njobs, uint32_t nblocks,
                      const sv::BucketJob* dcjobs, const uint32_t* dcblk2job, uint32_t ncblocks, uint32_t max_cbins,
-                     uint32_t gbins, uint32_t lds, uint32_t esz, uint32_t cap, hipStream_t s) {
+                     uint32_t gbins, uint32_t lds, uint32_t esz, uint32_t cap, hipStream_t s, bool logw = false) {
   uint32_t* HG = c->HG.as<uint32_t>();
   uint32_t* bst = c->bstart.as<uint32_t>();
   uint32_t* tot = bst + gbins + 1;
@@ -626,7 +630,12 @@ int bucket_fill_jobs(sieve_ctx* c, const sv::BucketJob* djobs, const uint32_t* d
   STCHK(launch(c, "k_bin_total", s, [&] { sv::k_bin_jobs<<<gb, 1024, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 0); }));
   STCHK(launch(c, "k_bin_scan", s, [&] { sv::k_bin_scan<<<1, 1024, 0, s>>>(tot, gbins, bst); }));
   STCHK(launch(c, "k_bin_colprefix", s, [&] { sv::k_bin_jobs<<<gb, 1024, 0, s>>>(HG, djobs, njobs, gbins, tot, bst, 1); }));
-  if (esz == 2)
+  if (logw)
+    STCHK(launch(c, "k_bucket_scatter", s, [&] {
+      sv::k_bucket_scatter2<uint32_t, true><<<nblocks, 1024, ls, s>>>(djobs, dblk2job, HG, bst, c->bucket.as<uint32_t>(),
+                                                                       cap, c->err.as<uint32_t>());
+    }));
+  else if (esz == 2)
     STCHK(launch(c, "k_bucket_scatter", s, [&] {
       sv::k_bucket_scatter2<uint16_t><<<nblocks, 1024, ls, s>>>(djobs, dblk2job, HG, bst, c->bucket.as<uint16_t>(),
                                                                  cap, c->err.as<uint32_t>());
@@ -828,6 +837,125 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
     else
       STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(c, L, s, ta); }));
+  }
+  return SIEVE_OK;
+}
+
+// The log-add sieve of (l, F, NB) with the odd primes <= B of pr (Section 5's wider
+// use of buckets): tiles of 2^L positions whose byte sums sit in LDS, the medium
+// primes (below 2^L) walked per tile from their first offsets in the window, the
+// larger ones counting-sorted into per-tile bins of 32-bit entries carrying their
+// weight, chunks of 2^11 bins; output the candidate table C (sum >= T), the ones per
+// segment and optionally the sums A.
+constexpr uint32_t kLogBinsLog = 11;
+int run_logsieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint64_t NB, uint64_t B, uint32_t T,
+                 uint32_t* C, uint32_t* counts, uint8_t* A, uint32_t L, uint32_t groups, uint32_t ranges, hipStream_t s) {
+  const uint64_t med_lim = 1ull << L;
+  const uint64_t tab_ub = std::min<uint64_t>(pi_upper(B), pi_upper(pr->B));
+  STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
+  sv::Plan* plan = c->plan.as<sv::Plan>();
+  STCHK(launch(c, "k_plan", s, [&] {
+    sv::k_plan<<<1, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, 3, 1ull << 9, 1ull << 9, med_lim,
+                               1ull << (L - 3), (uint32_t)tab_ub, plan);
+  }));
+  const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
+  STCHK(c->Q0.ensure(med_ub * 8 + 64));
+  const bool large = B >= med_lim;
+  const uint64_t nL_ub = large ? tab_ub : 0;
+  if (large) STCHK(c->OFF.ensure(2 * nL_ub * 4 + 64));
+  const uint32_t b = L, esz = 4;
+  const uint64_t chunk_max = std::min<uint64_t>(1ull << (kLogBinsLog + b), kLaunchBits);
+  struct Chunk { uint64_t ls, lbits, cs, cbits; uint32_t nbins, j0, j1, b0, b1, cj0, cb0, cb1, lds; };
+  std::vector<Chunk> chunks;
+  c->h_jobs.clear(); c->h_blk2job.clear(); c->h_cjobs.clear(); c->h_cblk2job.clear(); c->h_thr.clear();
+  uint64_t hg_max = 0, cap = 0, pad_max = 0;
+  uint32_t nbins_max = 0;
+  if (large) {
+    cap = (uint64_t)(1.02 * recip_sum_upper((double)med_lim, (double)B) * (double)std::min<uint64_t>(chunk_max, NB)) +
+          nL_ub + 4096;
+    if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
+  }
+  for (uint64_t ls = 0; ls < NB; ls += kLaunchBits) {
+    const uint64_t lbits = std::min<uint64_t>(kLaunchBits, NB - ls);
+    uint32_t off_cur = 0;
+    for (uint64_t cs = 0; cs < lbits; cs += chunk_max) {
+      Chunk ch;
+      ch.ls = ls; ch.lbits = lbits; ch.cs = cs; ch.cbits = std::min<uint64_t>(chunk_max, lbits - cs);
+      ch.nbins = (uint32_t)((ch.cbits + (1ull << b) - 1) >> b);
+      ch.j0 = (uint32_t)c->h_jobs.size(); ch.b0 = (uint32_t)c->h_blk2job.size();
+      ch.cj0 = (uint32_t)c->h_cjobs.size(); ch.cb0 = (uint32_t)c->h_cblk2job.size();
+      ch.lds = 0;
+      if (large) {
+        uint64_t hg = 0;
+        const uint32_t* oin = c->OFF.as<uint32_t>() + (size_t)off_cur * nL_ub;
+        uint32_t* oout = c->OFF.as<uint32_t>() + (size_t)(1 - off_cur) * nL_ub;
+        const size_t jb = c->h_jobs.size(), cjb = c->h_cjobs.size();
+        chunk_jobs(ch.nbins, (uint32_t)ch.cbits, b, ranges, groups, (double)med_lim, (double)B, pr->P.as<uint32_t>(),
+                   plan, oin, oout, 0, &c->h_jobs, &c->h_blk2job, &c->h_cjobs, &c->h_cblk2job, &c->h_thr, &hg, esz);
+        for (size_t k = jb; k < c->h_jobs.size(); ++k) c->h_jobs[k].block0 -= ch.b0;
+        for (size_t k = cjb; k < c->h_cjobs.size(); ++k) c->h_cjobs[k].block0 -= ch.cb0;
+        pad_max = std::max(pad_max, set_stages(c->h_jobs, jb, c->h_jobs.size(), esz, &ch.lds));
+        for (size_t k = ch.b0; k < c->h_blk2job.size(); ++k) c->h_blk2job[k] -= ch.j0;
+        for (size_t k = ch.cb0; k < c->h_cblk2job.size(); ++k) c->h_cblk2job[k] -= ch.cj0;
+        hg_max = std::max(hg_max, hg);
+        nbins_max = std::max(nbins_max, ch.nbins);
+        off_cur ^= 1u;
+      }
+      ch.j1 = (uint32_t)c->h_jobs.size(); ch.b1 = (uint32_t)c->h_blk2job.size();
+      ch.cb1 = (uint32_t)c->h_cblk2job.size();
+      chunks.push_back(ch);
+    }
+  }
+  if (large) {
+    cap += pad_max;
+    if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
+    STCHK(c->HG.ensure(hg_max * 4 + 64));
+    STCHK(c->bstart.ensure(((size_t)2 * nbins_max + 2) * 4));
+    STCHK(c->bucket.ensure(cap * esz));
+    STCHK(pin_begin(c, job_upload_bytes(c)));
+    STCHK(upload_jobs(c, s));
+    STCHK(pin_end(c, s));
+  }
+  STCHK(ensure_err(c, s));
+  if (l > L) {
+    const uint64_t n = NB >> l;
+    STCHK(launch(c, "k_fill_u32", s, [&] {
+      sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(counts, n, 0);
+    }));
+  }
+  const sv::BucketJob* djobs = c->jobs.as<sv::BucketJob>();
+  const uint32_t* dblk = c->blk2job.as<uint32_t>();
+  const sv::BucketJob* dcjobs = c->cjobs.as<sv::BucketJob>();
+  const uint32_t* dcblk = c->cblk2job.as<uint32_t>();
+  uint64_t cur_ls = ~0ull;
+  for (const Chunk& ch : chunks) {
+    const uint64_t G0 = F + ch.ls;
+    if (ch.ls != cur_ls) {
+      cur_ls = ch.ls;
+      STCHK(launch(c, "k_offsets", s, [&] {
+        sv::k_offsets<<<(uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), 256, 0, s>>>(
+            pr->P.as<uint32_t>(), plan, G0, ch.lbits, c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr, 0, 1);
+      }));
+    }
+    if (large)
+      STCHK(bucket_fill_jobs(c, djobs + ch.j0, dblk + ch.b0, ch.j1 - ch.j0, ch.b1 - ch.b0, dcjobs + ch.cj0, dcblk + ch.cb0,
+                             ch.cb1 - ch.cb0, ch.nbins, ch.nbins, ch.lds, esz, (uint32_t)cap, s, true));
+    sv::LogArgs a;
+    memset(&a, 0, sizeof a);
+    a.G0 = G0; a.lbits = (uint32_t)ch.lbits; a.t0 = (uint32_t)(ch.cs >> L); a.l = l; a.T = T;
+    a.QP = c->Q0.as<uint2>(); a.plan = plan;
+    a.bucket = large ? c->bucket.p : nullptr; a.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
+    a.nbins = ch.nbins; a.cap = (uint32_t)cap; a.has_large = large ? 1 : 0; a.count_atomic = l > L ? 1 : 0;
+    a.C = C + (ch.ls >> 5); a.counts = counts + (ch.ls >> l); a.A = A ? A + ch.ls : nullptr;
+    const uint32_t ntiles = (uint32_t)((ch.cbits + (1ull << L) - 1) >> L);
+    STCHK(launch(c, "k_logtile", s, [&] {
+      switch (L) {
+        case 14: sv::k_logtile<14><<<ntiles, 1024, 0, s>>>(a); break;
+        case 15: sv::k_logtile<15><<<ntiles, 1024, 0, s>>>(a); break;
+        case 16: sv::k_logtile<16><<<ntiles, 1024, 0, s>>>(a); break;
+        default: sv::k_logtile<17><<<ntiles, 1024, 0, s>>>(a); break;
+      }
+    }));
   }
   return SIEVE_OK;
 }
@@ -1617,4 +1745,28 @@ extern "C" int sieve_goldbach(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l
     sv::k_gb_finish<<<(uint32_t)((n + 255) / 256), 256, 0, s>>>(best, n, l, maxq_dev, argk_dev);
   }));
   return end(c, s);
+}
+
+extern "C" int sieve_logsieve(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, uint64_t f, uint64_t n, uint64_t B,
+                              uint32_t T, uint32_t* C_dev, uint32_t* counts_dev, uint8_t* A_dev,
+                              const sieve_tune* tune, void* stream) {
+  if (!ctx || !C_dev || !counts_dev || T > 255) return SIEVE_E_ARG;
+  uint64_t F, NB;
+  STCHK(check_interval(l, f, n, B, &F, &NB));
+  if (pr && B > pr->B) return SIEVE_E_BOUND;
+  const uint32_t L = tune && tune->tile_log2 ? tune->tile_log2 : 16;
+  if (L < 14 || L > 17) return SIEVE_E_ARG;
+  const uint32_t groups = tune && tune->groups ? tune->groups : 2048;
+  const uint32_t ranges = tune ? tune->ranges : 0;
+  if (groups < 64 || groups > 4096 || (ranges != 0 && ranges != 1 && ranges != 2 && ranges != 4 && ranges != 8))
+    return SIEVE_E_ARG;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(ctx, s));
+  if (!pr) {
+    STCHK(build_primes(ctx, B, &ctx->own, s));
+    pr = &ctx->own;
+  }
+  STCHK(run_logsieve(ctx, pr, l, F, NB, B, T, C_dev, counts_dev, A_dev, L, groups, ranges, s));
+  return end(ctx, s);
 }

@@ -61,3 +61,11 @@ def test_kernel_hash_ignores_comments(tmp_path):
     finally:
         bench.ROOT = old
     assert h0 == h1 and h1 != h2
+
+
+def test_log_adds_match_brute_force():
+    P = _primes(2000)
+    P = P[P >= 3]
+    for (u, v) in [(1, 20000), (99999, 130000), (10**9 + 1, 10**9 + 40000)]:
+        want = sum(1 for p in P for N in range(u, v + 1) if N % 2 and N % p == 0)
+        assert bench.log_adds(P, u, v) == want, (u, v)
