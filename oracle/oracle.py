@@ -48,6 +48,11 @@ def _load():
         lib.oracle_logsieve.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.c_uint32, u32p, u32p, ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_logsieve.restype = ctypes.c_int
+        lib.oracle_sieve_wide.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, u32p, u32p]
+        lib.oracle_sieve_wide.restype = ctypes.c_int
+        lib.oracle_odd_primes64.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64))]
+        lib.oracle_odd_primes64.restype = ctypes.c_longlong
         lib.oracle_odd_primes.argtypes = [ctypes.c_uint64, ctypes.POINTER(u32p)]
         lib.oracle_odd_primes.restype = ctypes.c_long
         lib.oracle_lemma1_offset.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
@@ -133,6 +138,32 @@ def logsieve(l, f, n, B, T, with_sums=True):
     if rc != 0:
         raise OracleError("oracle_logsieve(l=%d, f=%d, n=%d, B=%d, T=%d) -> %d" % (l, f, n, B, T, rc))
     return C[:nb // 32], c[:n], A
+
+
+def sieve_wide(l, f, n, B):
+    """Definition 1 for f up to 2^127 / 2^l (intervals past 2^64) and B up to 2^40:
+    returns (S as uint32 words, counts per segment)."""
+    lib = _load()
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    nwords = (n << l) // 32
+    S = np.zeros(max(nwords, 1), dtype=np.uint32)
+    c = np.zeros(max(n, 1), dtype=np.uint32)
+    rc = lib.oracle_sieve_wide(l, f & ((1 << 64) - 1), f >> 64, n, B, S.ctypes.data_as(u32p), c.ctypes.data_as(u32p))
+    if rc != 0:
+        raise OracleError("oracle_sieve_wide(l=%d, f=%d, n=%d, B=%d) -> %d" % (l, f, n, B, rc))
+    return S[:nwords], c[:n]
+
+
+def odd_primes64(B):
+    """Odd primes 3 <= p <= B (B <= 2^40) as uint64."""
+    lib = _load()
+    ptr = ctypes.POINTER(ctypes.c_uint64)()
+    cnt = lib.oracle_odd_primes64(B, ctypes.byref(ptr))
+    if cnt < 0:
+        raise OracleError("oracle_odd_primes64(%d) failed" % B)
+    out = np.ctypeslib.as_array(ptr, shape=(max(cnt, 1),))[:cnt].copy()
+    lib._free(ptr)
+    return out
 
 
 def odd_primes(B):

@@ -255,3 +255,72 @@ int oracle_logsieve(uint32_t l, uint64_t f, uint64_t n, uint64_t B, uint32_t T,
     free(acc);
     return OR_OK;
 }
+
+/* Odd primes 3 <= p <= B for B up to 2^40 (64-bit values), by the same plain sieve
+ * of Eratosthenes as oracle_odd_primes.  Returns the count or -1. */
+long long oracle_odd_primes64(uint64_t B, uint64_t **out)
+{
+    *out = NULL;
+    if (B < 3 || B > ((uint64_t)1 << 40)) { *out = (uint64_t *)malloc(8); return (B < 3 && *out) ? 0 : -1; }
+    uint64_t K = (B - 1) / 2 + 1;
+    unsigned char *comp = (unsigned char *)calloc(K, 1);
+    if (!comp) return -1;
+    for (uint64_t k = 1; k < K; ++k) {
+        if (comp[k]) continue;
+        uint64_t p = 2 * k + 1;
+        if (p * p > B) break;
+        for (uint64_t m = (p * p - 1) / 2; m < K; m += p) comp[m] = 1;
+    }
+    long long cnt = 0;
+    for (uint64_t k = 1; k < K; ++k) cnt += !comp[k];
+    uint64_t *pr = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(cnt > 0 ? cnt : 1));
+    if (!pr) { free(comp); return -1; }
+    long long w = 0;
+    for (uint64_t k = 1; k < K; ++k) if (!comp[k]) pr[w++] = 2 * k + 1;
+    free(comp);
+    *out = pr;
+    return cnt;
+}
+
+/* Definition 1 for intervals beyond 2^64 (Section 5: sieving with primes above 32
+ * bits): f is given as two 64-bit halves (f = f_hi * 2^64 + f_lo), so
+ * u = f*2^(l+1) + 1 and v = (f+n)*2^(l+1) may reach 2^128 - 2^(l+1); the bound
+ * B may reach 2^40.  The table is the same: bit j is set iff u + 2j == 1 or it has
+ * an odd prime divisor p <= B with p < u + 2j (every odd multiple m*p, m >= 3). */
+int oracle_sieve_wide(uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B,
+                      uint32_t *S, uint32_t *counts)
+{
+    if (l < 5 || l > 30 || n == 0) return OR_E_ARG;
+    if (B < 3 || B > ((uint64_t)1 << 40)) return OR_E_BOUND;
+    u128 f = ((u128)f_hi << 64) | f_lo;
+    if (f >> (127 - l)) return OR_E_RANGE;
+    u128 F = f << l, NB128 = (u128)n << l;
+    if (NB128 >> 40) return OR_E_ARG;
+    u128 vv = 2 * (F + NB128);
+    if (vv < 2 * F) return OR_E_RANGE;                  /* wrapped past 2^128 */
+    uint64_t NB = (uint64_t)NB128;
+    u128 u = 2 * F + 1, v = vv;
+    memset(S, 0, (size_t)(NB / 32) * 4);
+    uint64_t *P = NULL;
+    long long np = oracle_odd_primes64(B, &P);
+    if (np < 0) return OR_E_NOMEM;
+    for (long long i = 0; i < np; ++i) {
+        u128 p = P[i];
+        u128 m = (u + p - 1) / p;
+        if (m < 3) m = 3;
+        if ((m & 1) == 0) m += 1;
+        u128 N = m * p;
+        if (N > v) continue;
+        uint64_t j = (uint64_t)((N - u) / 2);
+        for (; j < NB; j += (uint64_t)p) S[j >> 5] |= 1u << (j & 31);
+    }
+    free(P);
+    if (u == 1) S[0] |= 1u;
+    uint64_t wps = ((uint64_t)1 << l) / 32;
+    for (uint64_t t = 0; t < n; ++t) {
+        uint64_t ones = 0;
+        for (uint64_t w = t * wps; w < (t + 1) * wps; ++w) ones += (uint64_t)__builtin_popcount(S[w]);
+        counts[t] = (uint32_t)(((uint64_t)1 << l) - ones);
+    }
+    return OR_OK;
+}

@@ -372,3 +372,27 @@ def test_logsieve_smooth_numbers():
         if prod == N:
             assert A[j] >= math.log2(N) - len(fs)
     assert A[0] == 0    # the number 1
+
+
+def test_sieve_wide_agrees_below_2_64_and_miller_rabin_above():
+    # below 2^64 the wide oracle is the plain one
+    for (l, f, n, B) in [(10, 0, 3, 100), (12, (10**15) >> 13, 2, 10**5), (20, 2**43 - 3, 1, 3000)]:
+        S0, c0 = O.sieve(l, f, n, B)
+        S1, c1 = O.sieve_wide(l, f, n, B)
+        assert np.array_equal(S0, S1) and np.array_equal(c0, c1)
+    # just past 2^64 with the bound isqrt(v), a little above 2^32: zero bits are exactly
+    # the primes (deterministic Miller-Rabin below 3.3e24)
+    l, n = 12, 1
+    f = (2**64 + 2**45) >> (l + 1)
+    u, v = O.interval(l, f, n)
+    B = math.isqrt(v)
+    assert B > 2**32 + 4000
+    S, c = O.sieve_wide(l, f, n, B)
+    bits = np.unpackbits(S.view(np.uint8), bitorder="little")
+    for j in range(n << l):
+        assert bool(bits[j]) == (not is_prime_mr(u + 2 * j)), j
+
+
+def test_odd_primes64_below_2_32_is_odd_primes():
+    for B in (3, 1000, 10**6 + 3):
+        assert np.array_equal(O.odd_primes64(B), O.odd_primes(B).astype(np.uint64))
