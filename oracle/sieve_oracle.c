@@ -306,12 +306,13 @@ int oracle_sieve_wide(uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint
     if (np < 0) return OR_E_NOMEM;
     for (long long i = 0; i < np; ++i) {
         u128 p = P[i];
-        u128 m = (u + p - 1) / p;
-        if (m < 3) m = 3;
-        if ((m & 1) == 0) m += 1;
-        u128 N = m * p;
-        if (N > v) continue;
-        uint64_t j = (uint64_t)((N - u) / 2);
+        /* the first odd multiple m*p >= u, m >= 3, as a distance from u (u + p
+         * itself may pass 2^128 when v is near it) */
+        u128 d = (p - u % p) % p;             /* u + d: the first multiple of p >= u */
+        if ((d & 1) != 0) d += p;             /* u odd: the first odd one */
+        if (u <= p && u + d == p) d += 2 * p; /* m = 1: p itself stays */
+        if (d / 2 >= NB) continue;
+        uint64_t j = (uint64_t)(d / 2);
         for (; j < NB; j += (uint64_t)p) S[j >> 5] |= 1u << (j & 31);
     }
     free(P);

@@ -393,6 +393,28 @@ def test_sieve_wide_agrees_below_2_64_and_miller_rabin_above():
         assert bool(bits[j]) == (not is_prime_mr(u + 2 * j)), j
 
 
+def test_sieve_wide_near_2_128_by_trial_division():
+    # v = 2^128 - 2^11: every sampled bit is 1 exactly when an odd prime p <= B divides
+    # its number (p below it); the residues come from the number's two 64-bit halves
+    # and 2^64 mod p, independently of the oracle's arithmetic
+    l, n, B = 10, 8, 2**20 + 7
+    f = 2**117 - 1 - n
+    u, v = f * 2**(l + 1) + 1, (f + n) * 2**(l + 1)
+    assert v == 2**128 - 2**11 and B > v - u
+    S, c = O.sieve_wide(l, f, n, B)
+    bits = np.unpackbits(S.view(np.uint8), bitorder="little")
+    P = O.odd_primes(B).astype(np.uint64)
+    t64 = (np.uint64(2**64 - 1) % P + np.uint64(1)) % P
+    rng = np.random.default_rng(128)
+    idx = sorted(set(rng.integers(0, n << l, 300).tolist()) | set(range(40)) | set(range((n << l) - 40, n << l)))
+    for j in idx:
+        N = u + 2 * j
+        hi, lo = np.uint64(N >> 64), np.uint64(N & (2**64 - 1))
+        r = ((hi % P) * t64 + lo % P) % P
+        assert bool(bits[j]) == bool((r == 0).any()), j
+    assert int(c.sum()) == (n << l) - int(bits.sum())
+
+
 def test_odd_primes64_below_2_32_is_odd_primes():
     for B in (3, 1000, 10**6 + 3):
         assert np.array_equal(O.odd_primes64(B), O.odd_primes(B).astype(np.uint64))
