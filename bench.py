@@ -592,6 +592,61 @@ def run_logsieve(steps, B=1 << 20, T=34):
                                   "(%.4g per call)" % adds)}
 
 
+def _probable_prime(N):
+    """Miller-Rabin to the first twelve prime bases (deterministic below 3.1e23)."""
+    small = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+    for p in small:
+        if N % p == 0:
+            return N == p
+    d, s = N - 1, 0
+    while d % 2 == 0:
+        d, s = d // 2, s + 1
+    for a in small:
+        x = pow(a, d, N)
+        if x in (1, N - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % N
+            if x == N - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def run_wide(steps, l=20, f=2**49, n=1024):
+    """The prime table of 2^30 odd numbers from 2^70 + 1 (beyond 2^64: a 128-bit
+    start, sieving primes up to isqrt(v) = 2^35, i.e. above 32 bits), timed per call;
+    600 sampled bits checked against Miller-Rabin (zero bit <=> prime)."""
+    import random
+    import numpy as np
+    import torch
+    from paper_1111_3297_amd import api
+    u, v = f * 2**(l + 1) + 1, (f + n) * 2**(l + 1)
+    B = math.isqrt(v) + 1
+    S, c = api.alloc(l, n)
+    ctx = api.Context()
+    stream = torch.cuda.current_stream()
+    call = lambda: ctx.wide(l, f, n, B, S, c)
+    for _ in range(2):
+        call()
+    lat, _ = _step_times(call, steps, stream)
+    kernels = _kernel_times(ctx, call, max(2, steps // 2))
+    ctx.check_device_errors()
+    Sh, ch = S.cpu().numpy().view(np.uint32), c.cpu().numpy().view(np.uint32)
+    rng = random.Random(70)
+    ok = True
+    for j in [rng.randrange(n << l) for _ in range(600)]:
+        ok = ok and (((int(Sh[j >> 5]) >> (j & 31)) & 1) == (0 if _probable_prime(u + 2 * j) else 1))
+    ms = sum(lat) / len(lat)
+    return {"workload": "prime table of the odd numbers 2^70 + 1 .. 2^70 + 2^31 (2^30 bits) with the odd "
+                        "primes up to %d (128-bit start, sieving primes above 32 bits)" % B,
+            "ms_per_call": ms, "p99_ms": _pct(lat, 0.99), "numbers_per_s": (v - u + 1) / (ms * 1e-3),
+            "primes": int(ch.astype(np.int64).sum()), "sampled_bits_match_miller_rabin": ok,
+            "kernels_ms_per_call": {k: round(x["total_ms"], 4) for k, x in kernels.items()},
+            "launches_per_call": {k: x["launches_per_step"] for k, x in kernels.items()}}
+
+
 def unit_rates():
     """Measured unit rates the roofline figures are set against: the library's LDS-atomic, VALU
     and 64-bit remainder microbenchmarks (sieve_microbench, median of three) and its plain HBM
@@ -662,6 +717,7 @@ def main():
     ap.add_argument("--latency-steps", type=int, default=200, help="calls of the small interval for launch latency")
     ap.add_argument("--goldbach-steps", type=int, default=10, help="timed Goldbach checks of the 1e12 table (0: skip)")
     ap.add_argument("--logsieve-steps", type=int, default=10, help="timed log-add sieves of the 1e12 interval (0: skip)")
+    ap.add_argument("--wide-steps", type=int, default=5, help="timed prime tables at 2^70 (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="seconds of the request stream to replay (0: skip)")
     ap.add_argument("--serve-speedups", default="10,30,100", help="time-compressed replays of the same stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -761,6 +817,9 @@ def main():
         log("log-add sieve")
         out["logsieve"] = run_logsieve(args.logsieve_steps)
         rooflines.append(dict(out["logsieve"]["roofline"], workload="logsieve_1e12"))
+    if args.wide_steps > 0:
+        log("prime table beyond 2^64")
+        out["wide"] = run_wide(args.wide_steps)
     out["also"] = also
     out["rooflines"] = rooflines
     if args.latency_steps > 0:

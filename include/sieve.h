@@ -224,6 +224,26 @@ int sieve_logsieve(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t 
                    uint64_t B, uint32_t T, uint32_t *C_dev, uint32_t *counts_dev, uint8_t *A_dev,
                    const sieve_tune *tune, void *stream);
 
+/* --- intervals beyond 2^64 (Section 5: sieving with primes of more than 32 bits,
+ * the extension the paper names for its 32-bit implementation) ---
+ * Definition 1 for the interval (l, f, n) with a 128-bit f = f_hi*2^64 + f_lo:
+ * u = f*2^(l+1) + 1 and v = (f+n)*2^(l+1) with 2^64 < u and v < 2^128 (the segment
+ * boundary 2^64 splits an interval that crosses it into a sieve_init part and a
+ * sieve_wide part).  The odd primes 3 <= p <= B sieve, with 3 <= B <= 2^40 (B may
+ * reach 2^32 and beyond: B >= isqrt(v) makes S an exact prime table up to
+ * v = 2^80).  Outputs as sieve_init: S_dev (n*2^l/32 words, bit j <-> u + 2j),
+ * counts_dev (n words).  Every p < 2^41 is below sqrt(u), so the p^2 start rule
+ * never applies.  The primes up to min(B, 2^32 - 1) take the path of
+ * sieve_ctx_sieve (the context's own table, first offsets from the 128-bit start);
+ * the primes above 2^32 are produced in slices of 2^30 odd numbers by sieving
+ * those numbers on the device (the context keeps one slice, 132 MiB at most), and
+ * each marks its hits in S directly (fewer than one per prime on average); the
+ * counts are then taken again from S.  Validity: 5 <= l <= 20, 1 <= n < 2^31,
+ * n*2^l < 2^40.  Errors: SIEVE_E_ARG (null pointers, l, n), SIEVE_E_RANGE (u below
+ * 2^64 or v not below 2^128), SIEVE_E_BOUND (B < 3 or B > 2^40). */
+int sieve_wide(sieve_ctx *ctx, uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B,
+               uint32_t *S_dev, uint32_t *counts_dev, void *stream);
+
 /* --- allocation-free one-shot entry point ---
  * For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  Same arguments, result

@@ -22,7 +22,7 @@ EXPORTS = [
     "sieve_strerror", "sieve_last_hip_error", "sieve_check_device_errors", "sieve_ctx_set_timing",
     "sieve_ctx_kernel_times", "sieve_default_ctx", "sieve_copy_calibration", "sieve_microbench",
     "sieve_debug_buckets", "sieve_init_noalloc", "sieve_sieve_scratch_bytes", "sieve_ctx_scratch_bytes",
-    "sieve_ctx_trim", "sieve_primes_bytes", "sieve_goldbach", "sieve_logsieve",
+    "sieve_ctx_trim", "sieve_primes_bytes", "sieve_goldbach", "sieve_logsieve", "sieve_wide",
 ]
 MB_LDS_OR_RANDOM, MB_LDS_OR_SPREAD, MB_VALU, MB_MOD64 = 0, 1, 2, 3
 
@@ -81,6 +81,7 @@ def load():
         "sieve_ctx_trim": (i32, [vp]),
         "sieve_goldbach": (i32, [vp, vp, u32, u64, u64, vp, u64, vp, vp, vp, vp, vp]),
         "sieve_logsieve": (i32, [vp, vp, u32, u64, u64, u64, u32, vp, vp, vp, ctypes.POINTER(Tune), vp]),
+        "sieve_wide": (i32, [vp, u32, u64, u64, u64, u64, vp, vp, vp]),
         "sieve_primes_bytes": (i32, [vp, ctypes.POINTER(u64)]),
         "sieve_required_bound": (i32, [u32, u64, u64, ctypes.POINTER(u64)]),
         "sieve_strerror": (ctypes.c_char_p, [i32]),

@@ -179,6 +179,7 @@ struct sieve_ctx {
   // batch scratch and the host copies of its tables
   DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, cjobs, cblk2job, thr;
   DevBuf gb_best, gb_k;   // Goldbach check: packed per-segment maxima, prime count
+  DevBuf wsl;             // intervals beyond 2^64: a sieved slice of the primes above 2^32
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk;
   std::vector<uint32_t> h_seg0;
@@ -205,7 +206,7 @@ struct sieve_ctx {
   void each_buf(F&& f) {
     DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
                       &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
-                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k};
+                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl};
     for (DevBuf* b : bufs) f(*b);
     for (auto& b : pat) f(b);
   }
@@ -673,8 +674,12 @@ size_t job_upload_bytes(const sieve_ctx* c) {
 }
 
 // The sieve proper for one request (l, F, NB) with the table pr and bound B.
+// wide (two words, lo then hi), when given, is the true 128-bit start F of an
+// interval beyond 2^64: the first offsets come from it, every p^2 start rule is off
+// (psq = 2^32 - 1) and F is a stand-in congruent to it modulo 3*5*...*47, which is
+// all the tile kernel reads of the start besides those rules.
 int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint64_t NB, uint64_t B,
-              uint32_t* S, uint32_t* counts, const Resolved& R, hipStream_t s) {
+              uint32_t* S, uint32_t* counts, const Resolved& R, hipStream_t s, const uint64_t* wide = nullptr) {
   const uint32_t L = R.L;
   const uint64_t wave_lim = 1ull << R.Wlog, wheel_lim = 1ull << R.Blog, med_lim = 1ull << R.Mlog;
   const uint64_t tab_ub = std::min<uint64_t>(pi_upper(B), pi_upper(pr->B));
@@ -701,10 +706,17 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       const uint64_t n = NB >> l;
       STCHK(launch(c, "k_fill_u32", s, [&] { sv::k_fill_u32<<<(uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), 256, 0, s>>>(counts, n, 0); }));
     }
-    STCHK(launch(c, "k_offsets", s, [&] {
-      sv::k_offsets<<<dim3((uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), nwin), 256, 0, s>>>(
-          pr->P.as<uint32_t>(), plan, F, kLaunchBits, c->Q0.as<uint2>(), nullptr, (uint32_t)med_ub);
-    }));
+    const dim3 og((uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), nwin);
+    if (wide)
+      STCHK(launch(c, "k_offsets_wide", s, [&] {
+        sv::k_offsets_wide<<<og, 256, 0, s>>>(pr->P.as<uint32_t>(), plan, wide[0], wide[1], kLaunchBits,
+                                              c->Q0.as<uint2>(), nullptr, (uint32_t)med_ub);
+      }));
+    else
+      STCHK(launch(c, "k_offsets", s, [&] {
+        sv::k_offsets<<<og, 256, 0, s>>>(pr->P.as<uint32_t>(), plan, F, kLaunchBits, c->Q0.as<uint2>(), nullptr,
+                                         (uint32_t)med_ub);
+      }));
     sv::TileArgs ta;
     memset(&ta, 0, sizeof ta);
     ta.G0 = F; ta.t0 = 0; ta.L = L; ta.l = l;
@@ -721,7 +733,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       W.G0 = F + ls;
       W.lbits = (uint32_t)lb;
       W.ntiles = (uint32_t)((lb + (1ull << L) - 1) >> L);
-      W.psq = (uint32_t)std::min<uint64_t>(isqrt_u64(2 * W.G0 + 1), 0xFFFFFFFFull);
+      W.psq = wide ? 0xFFFFFFFFu : (uint32_t)std::min<uint64_t>(isqrt_u64(2 * W.G0 + 1), 0xFFFFFFFFull);
       W.per_G0 = (uint32_t)(W.G0 % per);
       W.S = S + (ls >> 5);
       W.counts = counts + (ls >> l);
@@ -809,13 +821,20 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     if (ch.ls != cur_ls) {
       cur_ls = ch.ls;
       const uint64_t off_ub = tab_ub;  // grid over primes >= 17
-      STCHK(launch(c, "k_offsets", s, [&] {
-        sv::k_offsets<<<(uint32_t)((off_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits,
-                                                                       c->Q0.as<uint2>(), large ? c->OFF.as<uint32_t>() : nullptr,
-                                                                       0);
-      }));
+      const uint32_t og = (uint32_t)((off_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer));
+      uint32_t* off = large ? c->OFF.as<uint32_t>() : nullptr;
+      if (wide) {
+        const uint64_t lo = wide[0] + ch.ls, hi = wide[1] + (lo < wide[0] ? 1u : 0u);
+        STCHK(launch(c, "k_offsets_wide", s, [&] {
+          sv::k_offsets_wide<<<og, 256, 0, s>>>(pr->P.as<uint32_t>(), plan, lo, hi, ch.lbits, c->Q0.as<uint2>(), off, 0);
+        }));
+      } else {
+        STCHK(launch(c, "k_offsets", s, [&] {
+          sv::k_offsets<<<og, 256, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits, c->Q0.as<uint2>(), off, 0);
+        }));
+      }
     }
-    const uint64_t psq = isqrt_u64(2 * G0 + 1);
+    const uint64_t psq = wide ? 0xFFFFFFFFull : isqrt_u64(2 * G0 + 1);
     const uint32_t ntiles = (uint32_t)((ch.cbits + (1ull << L) - 1) >> L);
     if (large)
       STCHK(bucket_fill_jobs(c, djobs + ch.j0, dblk + ch.b0, ch.j1 - ch.j0, ch.b1 - ch.b0, dcjobs + ch.cj0, dcblk + ch.cb0,
@@ -1769,4 +1788,77 @@ extern "C" int sieve_logsieve(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l
   }
   STCHK(run_logsieve(ctx, pr, l, F, NB, B, T, C_dev, counts_dev, A_dev, L, groups, ranges, s));
   return end(ctx, s);
+}
+
+// Intervals beyond 2^64 (Section 5 names sieving with primes of up to 64 bits as
+// the extension of the 32-bit implementation).  The 32-bit primes take the
+// ordinary path with 128-bit first offsets; the primes above 2^32 are produced a
+// slice at a time by sieving the odd numbers above 2^32 (with the primes up to the
+// slice's square root, Section 1.4) and mark the table directly; the counts are
+// then taken again.
+namespace {
+constexpr uint64_t kWideMaxB = 1ull << 40;
+constexpr uint32_t kSliceLog = 20;                // segment size of a slice sieve
+constexpr uint64_t kSliceBits = 1ull << 30;       // odd numbers per slice
+// 3*5*7*...*47: the tile kernel reads the start of the interval only modulo the
+// pattern periods (divisors of 3*5*7*11*13 and of 17*19*23, 29*31*37, 41*43*47)
+constexpr uint64_t kProxyMod = 307444891294245705ull;
+
+int check_wide(uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B, uint64_t* Flo, uint64_t* Fhi,
+               uint64_t* NB) {
+  if (l < 5 || l > 20 || n == 0) return SIEVE_E_ARG;
+  if (B < 3 || B > kWideMaxB) return SIEVE_E_BOUND;
+  if ((n >> (40 - l)) || (n >> 31)) return SIEVE_E_ARG;
+  typedef unsigned __int128 u128;
+  const u128 f = ((u128)f_hi << 64) | f_lo;
+  if (f >> (127 - l)) return SIEVE_E_RANGE;
+  const u128 F = f << l, N = (u128)n << l;
+  if ((F >> 63) == 0) return SIEVE_E_RANGE;         // u = 2F + 1 below 2^64
+  if ((F + N) >> 127) return SIEVE_E_RANGE;         // v = 2(F + NB) not below 2^128
+  *Flo = (uint64_t)F; *Fhi = (uint64_t)(F >> 64); *NB = (uint64_t)N;
+  return SIEVE_OK;
+}
+}  // namespace
+
+extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B,
+                          uint32_t* S_dev, uint32_t* counts_dev, void* stream) {
+  if (!ctx || !S_dev || !counts_dev) return SIEVE_E_ARG;
+  uint64_t W[2], NB;
+  STCHK(check_wide(l, f_lo, f_hi, n, B, &W[0], &W[1], &NB));
+  Resolved R, Rs;
+  STCHK(resolve_tune(l, nullptr, &R));
+  STCHK(resolve_tune(kSliceLog, nullptr, &Rs));
+  typedef unsigned __int128 u128;
+  const uint64_t Fp = kProxyMod + (uint64_t)((((u128)W[1] << 64) | W[0]) % kProxyMod);
+  const uint64_t B32 = std::min<uint64_t>(B, 0xFFFFFFFFull);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  sieve_ctx* c = ctx;
+  hipStream_t s = (hipStream_t)stream;
+  STCHK(begin(c, s));
+  STCHK(build_primes(c, B32, &c->own, s));
+  STCHK(run_sieve(c, &c->own, l, Fp, NB, B32, S_dev, counts_dev, R, s, W));
+  if (B > 0xFFFFFFFFull) {
+    const uint64_t k_lo = 1ull << 31, k_hi = (B - 1) / 2;     // indices of 2^32 + 1 and of the last odd <= B
+    const uint64_t need = std::min<uint64_t>(kSliceBits, ((k_hi - k_lo + 1 + (1ull << kSliceLog) - 1) >> kSliceLog) << kSliceLog);
+    STCHK(c->wsl.ensure(need / 8 + (need >> kSliceLog) * 4 + 256));
+    uint32_t* sl = c->wsl.as<uint32_t>();
+    uint32_t* slc = sl + need / 32;
+    for (uint64_t Fs = k_lo; Fs <= k_hi; Fs += kSliceBits) {
+      const uint64_t NBs = std::min<uint64_t>(need, ((k_hi - Fs + 1 + (1ull << kSliceLog) - 1) >> kSliceLog) << kSliceLog);
+      const uint64_t Bs = std::max<uint64_t>(3, isqrt_u64(2 * (Fs + NBs)));
+      STCHK(run_sieve(c, &c->own, kSliceLog, Fs, NBs, Bs, sl, slc, Rs, s));
+      const uint32_t nw = (uint32_t)(NBs / 32);
+      // remainder digits as wide as p < 2^(53-D) allows: 7, 8 or 11 steps
+      STCHK(launch(c, "k_wide_hits", s, [&] {
+        const uint32_t g = (nw + 255) / 256;
+        if (B <= (1ull << 33)) sv::k_wide_hits<20><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
+        else if (B <= (1ull << 36)) sv::k_wide_hits<17><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
+        else sv::k_wide_hits<12><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
+      }));
+    }
+    const uint32_t nseg = (uint32_t)n;
+    const uint32_t grid = l >= 13 ? nseg : (nseg + 255) / 256;
+    STCHK(launch(c, "k_recount", s, [&] { sv::k_recount<<<grid, 256, 0, s>>>(S_dev, l, nseg, counts_dev); }));
+  }
+  return end(c, s);
 }

@@ -16,6 +16,14 @@ Workloads (interval parameters of Section 1.2.1):
   serve_req6388    : request 6388 of the stream, its largest bound:
                      B = isqrt(v) = 2133783848
   interval_2p64_top: l=20, n=64 ending at v = 2^64 - 2^21, B = isqrt(v) = 2^32 - 1
+  wide_2p66        : beyond 2^64 (128-bit f): l=16, f=2^49-128, n=128 ending at
+                     v = 2^66, B = 2^33 = isqrt(v) (primes above 32 bits sieve)
+  wide_b32         : l=14, f=2^90+12345, n=64, B = 2^32 - 1 (every 32-bit prime)
+  wide_top         : l=12, f=2^115-41, n=40 ending at v = 2^128 - 2^13,
+                     B = 2^32 + 2^28 + 1 (partial; primes on both sides of 2^32)
+  wide_u2p64       : l=20, f=2^43 (u = 2^64 + 1), n=16, B = 2^32 + 2^30 + 3
+  wide_2p66_2g     : l=20, f=2^45-2048, n=2048 (2^31 bits) ending at v = 2^66,
+                     B = 2^33: about one hit per two primes above 2^32
   primes_2133783848, primes_4294967295: the odd primes <= B (count and SHA-256
                      of the ascending little-endian uint32 array)
   batch_1234       : the 256 interval requests of the seeded batch workload
@@ -51,6 +59,31 @@ def workloads():
         "serve_req6388": (20, 2171055560302, 128, 2133783848),
         "interval_2p64_top": (20, 2**43 - 65, 64, 2**32 - 1),
     }
+
+
+def wide_workloads():
+    return {
+        "wide_2p66": (16, 2**49 - 128, 128, 2**33),
+        "wide_b32": (14, 2**90 + 12345, 64, 2**32 - 1),
+        "wide_top": (12, 2**115 - 41, 40, 2**32 + 2**28 + 1),
+        "wide_u2p64": (20, 2**43, 16, 2**32 + 2**30 + 3),
+        "wide_2p66_2g": (20, 2**45 - 2048, 2048, 2**33),
+    }
+
+
+def wide_golden(name):
+    l, f, n, B = wide_workloads()[name]
+    t = time.time()
+    S, c = O.sieve_wide(l, f, n, B)
+    dt = time.time() - t
+    rec = {"name": name, "l": l, "f": str(f), "n": n, "B": B,
+           "u": str(f * 2**(l + 1) + 1), "v": str((f + n) * 2**(l + 1)),
+           "S_sha256": hashlib.sha256(S.tobytes()).hexdigest(),
+           "total_zero_bits": int(c.sum()), "counts": [int(x) for x in c],
+           "oracle_seconds": round(dt, 1)}
+    with open(os.path.join(HERE, name + ".json"), "w") as fh:
+        json.dump(rec, fh)
+    print(name, rec["total_zero_bits"], round(dt, 1), "s", flush=True)
 
 
 def prime_golden(B):
@@ -132,7 +165,9 @@ def main(names):
         return
     for name in [x for x in names if x.startswith("primes_")]:
         prime_golden(int(name.split("_")[1]))
-    names = [x for x in names if not x.startswith("primes_")] if names else None
+    for name in [x for x in names if x.startswith("wide_")]:
+        wide_golden(name)
+    names = [x for x in names if not x.startswith(("primes_", "wide_"))] if names else None
     if names == []:
         return
     for name in names or list(W):

@@ -57,6 +57,22 @@ def test_argument_errors_without_gpu():
     assert lib.sieve_init_noalloc(20, 0, 8193, 1000, dummy, dummy, None) == E["SIEVE_E_SCRATCH"]
     assert lib.sieve_init_noalloc(20, 0, 1, 1000, None, dummy, None) == E["SIEVE_E_ARG"]
     assert lib.sieve_init_noalloc(10, 0, 1, 2, dummy, dummy, None) == E["SIEVE_E_BOUND"]
+    # intervals beyond 2^64: checked before the context is used
+    ctx = ctypes.c_void_p()
+    assert lib.sieve_ctx_create(ctypes.byref(ctx)) == 0
+    M = (1 << 64) - 1
+    assert lib.sieve_wide(ctx, 12, (2**51 - 1) & M, 0, 4, 1000, dummy, dummy, None) == E["SIEVE_E_RANGE"]
+    assert lib.sieve_wide(ctx, 12, (2**115 - 4) & M, (2**115 - 4) >> 64, 4, 1000, dummy, dummy,
+                          None) == E["SIEVE_E_RANGE"]
+    assert lib.sieve_wide(ctx, 12, 0, 1 << 52, 4, 1000, dummy, dummy, None) == E["SIEVE_E_RANGE"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2**40 + 1, dummy, dummy, None) == E["SIEVE_E_BOUND"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2, dummy, dummy, None) == E["SIEVE_E_BOUND"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 0, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(ctx, 21, 2**51, 0, 4, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(ctx, 10, 2**53, 0, 2**30, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 1000, None, dummy, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(None, 12, 2**51, 0, 4, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_ctx_destroy(ctx) == 0
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
