@@ -25,13 +25,18 @@ def default_cache_path():
     return os.environ.get(CACHE_ENV, os.path.join(os.path.expanduser("~"), ".cache", "sieve_mi355x_autotune.json"))
 
 
+# Version of the candidate sets below: part of every cache key, so that entries
+# timed over an older set of candidates are tuned again.
+TUNER_VERSION = 2
+
+
 def signature(l, reqs):
-    """Coarse workload class: segment size, request count, total table bits and
-    largest bound, each rounded to a power of two."""
+    """Coarse workload class: tuner version, segment size, request count, total
+    table bits and largest bound, each rounded to a power of two."""
     bits = sum(n << l for (_, n, _) in reqs)
     bmax = max(B for (_, _, B) in reqs)
-    return "l=%d|nreq=%d|bits=2^%d|B=2^%d" % (l, 1 << max(0, (len(reqs) - 1).bit_length()),
-                                              max(0, bits - 1).bit_length(), max(0, bmax - 1).bit_length())
+    return "v%d|l=%d|nreq=%d|bits=2^%d|B=2^%d" % (TUNER_VERSION, l, 1 << max(0, (len(reqs) - 1).bit_length()),
+                                                  max(0, bits - 1).bit_length(), max(0, bmax - 1).bit_length())
 
 
 def candidates(l, bmax):
