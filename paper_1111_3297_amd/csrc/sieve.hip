@@ -1850,7 +1850,7 @@ extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_
       const uint32_t nw = (uint32_t)(NBs / 32);
       // remainder digits as wide as p < 2^(53-D) allows: 7, 8 or 11 steps
       STCHK(launch(c, "k_wide_hits", s, [&] {
-        const uint32_t g = (nw + 255) / 256;
+        const uint32_t g = (nw + 256 * sv::kWideRounds - 1) / (256 * sv::kWideRounds);
         if (B <= (1ull << 33)) sv::k_wide_hits<20><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
         else if (B <= (1ull << 36)) sv::k_wide_hits<17><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
         else sv::k_wide_hits<12><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
