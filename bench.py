@@ -36,6 +36,7 @@ HBM_PEAK = 8.0e12                           # bytes/s, published HBM3E peak
 BUCKET_BYTES_PER_HIT = 8                    # the method's bucket entry (prime, offset), written once per hit
 VALU_LANE_OPS = CUS * CLOCK_HZ * 64         # one wave64 32-bit VALU instruction per clock per CU
 GB_TEST_PEAK = 32 * VALU_LANE_OPS           # Goldbach tests: 32 even numbers per 32-bit AND
+FP64_OPS = 78.6e12 / 2                      # published fp64 vector peak, an fma counted as two flops
 
 
 def marks_algorithmic(primes, u, v):
@@ -91,7 +92,8 @@ def kernel_source_hash():
     comment-only edit keeps the committed counter summaries valid."""
     import re
     h = hashlib.sha256()
-    for rel in ("paper_1111_3297_amd/csrc/kernels.inc", "paper_1111_3297_amd/csrc/sieve.hip"):
+    for rel in ("paper_1111_3297_amd/csrc/kernels.inc", "paper_1111_3297_amd/csrc/logsieve.inc",
+                "paper_1111_3297_amd/csrc/sieve.hip"):
         with open(os.path.join(ROOT, rel)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
@@ -639,12 +641,31 @@ def run_wide(steps, l=20, f=2**49, n=1024):
     for j in [rng.randrange(n << l) for _ in range(600)]:
         ok = ok and (((int(Sh[j >> 5]) >> (j & 31)) & 1) == (0 if _probable_prime(u + 2 * j) else 1))
     ms = sum(lat) / len(lat)
+    # remainders the method takes: one per prime above 2^32 up to B (Lemma 1's first
+    # offset), B = 2^35 + 1 here (divisible by 3), pi(2^35) - pi(2^32) by the published
+    # values (OEIS A007053); each needs at least the Horner steps of a 128-bit start of
+    # this size (the top 52 bits, then 17-bit digits) at four fp64 operations per step,
+    # plus the reciprocal: the fp64 peak 78.6 TFLOP/s counts an fma as two, so
+    # 39.3e12 operations per second
+    assert B == 2**35 + 1
+    nrem = 1480206279 - 203280221
+    steps = 1 + max(0, -(-((f << l).bit_length() - 52) // 17))
+    ops = 4 * steps + 1
+    kw = kernels["k_wide_hits"]
+    peak = FP64_OPS / ops
+    roof = {"bound": "alu", "kernel": "k_wide_hits", "unit": "Gremainders/s",
+            "achieved": nrem / (kw["total_ms"] * 1e-3) / 1e9, "peak": peak / 1e9,
+            "frac": nrem / (kw["total_ms"] * 1e-3) / peak,
+            "per_call": {"remainders": nrem, "ms": kw["total_ms"], "launches": kw["launches_per_step"],
+                         "what": "one 128-bit remainder per prime in (2^32, B] (%d fp64 operations each at "
+                                 "the peak), plus its hits OR-ed into the table" % ops}}
     return {"workload": "prime table of the odd numbers 2^70 + 1 .. 2^70 + 2^31 (2^30 bits) with the odd "
                         "primes up to %d (128-bit start, sieving primes above 32 bits)" % B,
             "ms_per_call": ms, "p99_ms": _pct(lat, 0.99), "numbers_per_s": (v - u + 1) / (ms * 1e-3),
             "primes": int(ch.astype(np.int64).sum()), "sampled_bits_match_miller_rabin": ok,
             "kernels_ms_per_call": {k: round(x["total_ms"], 4) for k, x in kernels.items()},
-            "launches_per_call": {k: x["launches_per_step"] for k, x in kernels.items()}}
+            "launches_per_call": {k: x["launches_per_step"] for k, x in kernels.items()},
+            "roofline": roof}
 
 
 def unit_rates():
@@ -820,6 +841,7 @@ def main():
     if args.wide_steps > 0:
         log("prime table beyond 2^64")
         out["wide"] = run_wide(args.wide_steps)
+        rooflines.append(dict(out["wide"]["roofline"], workload="wide_2p70"))
     out["also"] = also
     out["rooflines"] = rooflines
     if args.latency_steps > 0:

@@ -48,7 +48,7 @@ def test_kernel_hash_ignores_comments(tmp_path):
     src = os.path.join(ROOT, "paper_1111_3297_amd", "csrc")
     d = tmp_path / "paper_1111_3297_amd" / "csrc"
     d.mkdir(parents=True)
-    for name in ("kernels.inc", "sieve.hip"):
+    for name in ("kernels.inc", "logsieve.inc", "sieve.hip"):
         text = open(os.path.join(src, name)).read()
         (d / name).write_text("// an added comment\n" + text.replace("\n", "\n  ", 3) + "\n/* trailing */\n")
     h0 = bench.kernel_source_hash()
