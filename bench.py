@@ -625,7 +625,7 @@ def run_wide(steps, l=20, f=2**49, n=1024):
     import torch
     from paper_1111_3297_amd import api
     u, v = f * 2**(l + 1) + 1, (f + n) * 2**(l + 1)
-    B = math.isqrt(v) + 1
+    B = math.isqrt(v)
     S, c = api.alloc(l, n)
     ctx = api.Context()
     stream = torch.cuda.current_stream()
@@ -642,12 +642,12 @@ def run_wide(steps, l=20, f=2**49, n=1024):
         ok = ok and (((int(Sh[j >> 5]) >> (j & 31)) & 1) == (0 if _probable_prime(u + 2 * j) else 1))
     ms = sum(lat) / len(lat)
     # remainders the method takes: one per prime above 2^32 up to B (Lemma 1's first
-    # offset), B = 2^35 + 1 here (divisible by 3), pi(2^35) - pi(2^32) by the published
-    # values (OEIS A007053); each needs at least the Horner steps of a 128-bit start of
-    # this size (the top 52 bits, then 17-bit digits) at four fp64 operations per step,
-    # plus the reciprocal: the fp64 peak 78.6 TFLOP/s counts an fma as two, so
-    # 39.3e12 operations per second
-    assert B == 2**35 + 1
+    # offset), B = 2^35 here, pi(2^35) - pi(2^32) by the published values (OEIS
+    # A007053); each needs at least the Horner steps of a 128-bit start of this size
+    # (the top 52 bits, then 17-bit digits) at four fp64 operations per step, plus the
+    # reciprocal: the fp64 peak 78.6 TFLOP/s counts an fma as two, so 39.3e12
+    # operations per second
+    assert B == 2**35
     nrem = 1480206279 - 203280221
     steps = 1 + max(0, -(-((f << l).bit_length() - 52) // 17))
     ops = 4 * steps + 1

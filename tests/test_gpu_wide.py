@@ -129,11 +129,12 @@ def _is_probable_prime(N):
 
 
 def test_wide_bench_size_sampled():
-    # the benchmarked configuration: 2^30 bits from u = 2^70 + 1, B = 2^35 = isqrt(v)
-    # rounded up, so a bit is zero exactly when its number is prime
+    # the benchmarked configuration: 2^30 bits from u = 2^70 + 1, B = isqrt(v) = 2^35,
+    # so a bit is zero exactly when its number is prime
     l, f, n = 20, 2**49, 1024
     u, v = f * 2**(l + 1) + 1, (f + n) * 2**(l + 1)
-    B = math.isqrt(v) + 1
+    B = math.isqrt(v)
+    assert B == 2**35
     say("wide sampled l=%d f=%d n=%d B=%d" % (l, f, n, B))
     S, c = gpu_wide(l, f, n, B)
     rng = random.Random(70)
