@@ -24,6 +24,7 @@ Workloads (interval parameters of Section 1.2.1):
   wide_u2p64       : l=20, f=2^43 (u = 2^64 + 1), n=16, B = 2^32 + 2^30 + 3
   wide_2p66_2g     : l=20, f=2^45-2048, n=2048 (2^31 bits) ending at v = 2^66,
                      B = 2^33: about one hit per two primes above 2^32
+  wide_2p68        : l=16, f=2^51-128, n=128 ending at v = 2^68, B = 2^34 = isqrt(v)
   primes_2133783848, primes_4294967295: the odd primes <= B (count and SHA-256
                      of the ascending little-endian uint32 array)
   batch_1234       : the 256 interval requests of the seeded batch workload
@@ -68,6 +69,7 @@ def wide_workloads():
         "wide_top": (12, 2**115 - 41, 40, 2**32 + 2**28 + 1),
         "wide_u2p64": (20, 2**43, 16, 2**32 + 2**30 + 3),
         "wide_2p66_2g": (20, 2**45 - 2048, 2048, 2**33),
+        "wide_2p68": (16, 2**51 - 128, 128, 2**34),
     }
 
 

@@ -92,7 +92,7 @@ def _golden(name):
         return json.load(fh)
 
 
-@pytest.mark.parametrize("name", ["wide_2p66", "wide_b32", "wide_top", "wide_u2p64", "wide_2p66_2g"])
+@pytest.mark.parametrize("name", ["wide_2p66", "wide_b32", "wide_top", "wide_u2p64", "wide_2p66_2g", "wide_2p68"])
 def test_wide_against_oracle_golden(name):
     g = _golden(name)
     l, f, n, B = g["l"], int(g["f"]), g["n"], g["B"]
