@@ -214,10 +214,11 @@ int sieve_goldbach(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t 
  *              u + 2j is at least T (0 <= T <= 255), a smoothness candidate;
  *   counts_dev (n uint32): the ones of C per segment;
  *   A_dev      (optional, NULL or n*2^l bytes): the sums themselves.
- * Tiles of 2^tile_log2 positions (14..17, default 16; tune may be NULL) hold their
+ * Tiles of 2^tile_log2 positions (14..17, default 17; tune may be NULL) hold their
  * byte sums in LDS; primes below the tile size are walked per tile, larger ones go
  * through the buckets of Sections 2.2-2.5 with their weight in the entry (groups
- * and ranges of the tune apply to that fill; the other fields are ignored).
+ * and ranges of the tune apply to that fill, by default 4 ranges sharing 1024
+ * workgroups; the other fields are ignored).
  * Errors as sieve_ctx_sieve, SIEVE_E_ARG also for T > 255 or a tile size out of
  * range; bucket overflow sets the device error word. */
 int sieve_logsieve(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t f, uint64_t n,

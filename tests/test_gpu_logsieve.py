@@ -49,14 +49,22 @@ def test_logsieve_cases(case):
     check(*case)
 
 
-@pytest.mark.parametrize("tile", [14, 15, 17])
+@pytest.mark.parametrize("tile", [14, 15, 16, 17])
 def test_logsieve_tile_sizes(tile):
     check(17, (10**11) >> 18, 6, 300007, 25, tune={"tile_log2": tile})
 
 
+@pytest.mark.parametrize("tune", [{"groups": 256}, {"tile_log2": 16, "ranges": 2, "groups": 2048},
+                                  {"ranges": 1, "groups": 64}, {"ranges": 8}])
+def test_logsieve_bucket_layouts(tune):
+    check(18, (10**12) >> 19, 40, 2 * 10**6 + 11, 28, tune=tune)
+
+
 def test_logsieve_multi_chunk_and_windows():
     # 2^28 positions: two chunks of 2^11 bins of 2^16 positions, B well past the tile
-    check(20, (10**13) >> 21, 256, 3 * 10**6, 32, tune={"groups": 256})
+    check(20, (10**13) >> 21, 256, 3 * 10**6, 32, tune={"tile_log2": 16, "groups": 256})
+    # 2^29 positions at the default tiles of 2^17: two chunks of 2^11 bins
+    check(20, (10**13) >> 21, 512, 3 * 10**6, 32)
 
 
 def test_logsieve_full_size_sampled_segments():
