@@ -180,6 +180,7 @@ struct sieve_ctx {
   DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, cjobs, cblk2job, thr;
   DevBuf gb_best, gb_k;   // Goldbach check: packed per-segment maxima, prime count
   DevBuf wsl;             // intervals beyond 2^64: a sieved slice of the primes above 2^32
+  DevBuf logpat;          // log-add sieve: weights of 3..13 over one period
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk;
   std::vector<uint32_t> h_seg0;
@@ -206,7 +207,7 @@ struct sieve_ctx {
   void each_buf(F&& f) {
     DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
                       &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
-                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl};
+                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl, &logpat};
     for (DevBuf* b : bufs) f(*b);
     for (auto& b : pat) f(b);
   }
@@ -874,8 +875,14 @@ int run_logsieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, u
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
-    sv::k_plan<<<1, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, 3, 1ull << 9, 1ull << 9, med_lim,
+    sv::k_plan<<<1, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, 17, 1ull << 9, 1ull << 9, med_lim,
                                1ull << (L - 3), (uint32_t)tab_ub, plan);
+  }));
+  // the weights of the primes 3..13 up to B, one period, with which every tile starts
+  const uint32_t nsmall = (B >= 3) + (B >= 5) + (B >= 7) + (B >= 11) + (B >= 13);
+  STCHK(c->logpat.ensure(sv::kLogPatWords * 4));
+  STCHK(launch(c, "k_logpattern", s, [&] {
+    sv::k_logpattern<<<(sv::kLogPatWords + 255) / 256, 256, 0, s>>>(c->logpat.as<uint32_t>(), nsmall);
   }));
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
   STCHK(c->Q0.ensure(med_ub * 8 + 64));
@@ -966,6 +973,7 @@ int run_logsieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, u
     a.bucket = large ? c->bucket.p : nullptr; a.bin_start = large ? c->bstart.as<uint32_t>() : nullptr;
     a.nbins = ch.nbins; a.cap = (uint32_t)cap; a.has_large = large ? 1 : 0; a.count_atomic = l > L ? 1 : 0;
     a.C = C + (ch.ls >> 5); a.counts = counts + (ch.ls >> l); a.A = A ? A + ch.ls : nullptr;
+    a.pat = c->logpat.as<uint32_t>();
     const uint32_t ntiles = (uint32_t)((ch.cbits + (1ull << L) - 1) >> L);
     STCHK(launch(c, "k_logtile", s, [&] {
       switch (L) {
