@@ -49,6 +49,14 @@ def test_logsieve_cases(case):
     check(*case)
 
 
+@pytest.mark.parametrize("B", [4, 5, 6, 7, 10, 11, 12, 13, 16, 17, 19])
+def test_logsieve_small_prime_pattern_bounds(B):
+    # the weights of 3..13 come from a periodic pattern holding only the primes up
+    # to B; from the number 1 (the primes count themselves) and far from it
+    check(10, 0, 4, B, 1)
+    check(12, 15015 * 1000 + 77, 3, B, 2)
+
+
 @pytest.mark.parametrize("tile", [14, 15, 16, 17])
 def test_logsieve_tile_sizes(tile):
     check(17, (10**11) >> 18, 6, 300007, 25, tune={"tile_log2": tile})
