@@ -68,6 +68,31 @@ def test_goldbach_cases(case):
     check(l, f, n, B, Q)
 
 
+@pytest.mark.parametrize("case", [
+    (5, 0, 40, 100, 97),
+    (12, 0, 9, 4096, 1621),
+    (12, 11, 9, 4096, 1627),
+    (13, (10**9) >> 14, 5, 0, 13),
+    (14, (10**9) >> 15, 3, 0, 40000),
+    (16, (10**12) >> 17, 8, 0, 1 << 16),
+    (20, (10**15) >> 21, 2, 0, 5000),
+    (15, 0, 64, 2048, 2048),
+    (11, 1, 3, 300, 5000),
+])
+def test_goldbach_segment_outputs_only(case):
+    # the kernel without per-number output (the benchmarked one): per-segment
+    # maximum, first argument and failures against the oracle's
+    l, f, n, B, Q = case
+    if B == 0:
+        B = math.isqrt(O.interval(l, f, n)[1])
+    say("goldbach segments l=%d f=%d n=%d B=%d Q=%d" % (l, f, n, B, Q))
+    S, _, maxq, argk, fails = gpu_goldbach(l, f, n, B, Q, per_number=False)
+    So, _ = O.sieve(l, f, n, B)                 # the oracle's own table
+    assert first_diff(S, So) is None
+    _, mx, ak, fl = O.goldbach(l, f, n, So, Q, per_number=False)
+    assert np.array_equal(maxq, mx) and np.array_equal(argk, ak) and np.array_equal(fails, fl)
+
+
 def test_goldbach_full_size_sampled_segments():
     # the 2^33-number table at 1e12 (B = isqrt(v)), Q = 2^16, segment outputs only;
     # sampled segments recomputed by the oracle on a two-segment table that starts one
