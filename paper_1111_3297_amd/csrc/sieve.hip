@@ -55,7 +55,7 @@ thread_local bool g_in_call = false;
 
 constexpr uint64_t kLaunchBits = sv::kWinBits;  // offsets of one launch window fit 32 bits
 constexpr uint32_t kGenTile = 20;             // largest tile of the prime generator
-constexpr uint32_t kBatchRun = 4;             // most consecutive tiles per batch work item
+constexpr uint32_t kBatchRunMax = 16;         // most consecutive tiles per batch work item
 constexpr uint32_t kAutoRangeBins = 1024;      // chunks with this many bins or more use two bin ranges by default
 constexpr double kHitsPerGroup = 16384.0;      // fewest expected hits per bucket-fill workgroup
 constexpr uint32_t kMaxCountBins = 32768;      // bins of one count job (its LDS histogram: 128 KB)
@@ -177,12 +177,12 @@ struct sieve_ctx {
   // scratch
   DevBuf plan, Q0, OFF, HG, PS, bstart, bucket, err, gen_S, gen_blk, mb_sink;
   // batch scratch and the host copies of its tables
-  DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, jobs, blk2job, cjobs, cblk2job, thr;
+  DevBuf b_req, b_blk, b_seg0, b_tcnt, b_queue, b_items, jobs, blk2job, cjobs, cblk2job, thr;
   DevBuf gb_best, gb_k;   // Goldbach check: packed per-segment maxima, prime count
   DevBuf wsl;             // intervals beyond 2^64: a sieved slice of the primes above 2^32
   DevBuf logpat;          // log-add sieve: weights of 3..13 over one period
   std::vector<sv::BatchReq> h_req;
-  std::vector<uint2> h_blk;
+  std::vector<uint2> h_blk, h_items;
   std::vector<uint32_t> h_seg0;
   std::vector<sv::BucketJob> h_jobs, h_cjobs;           // scatter jobs (bin ranges), count jobs (whole chunks)
   std::vector<uint32_t> h_blk2job, h_cblk2job, h_thr;
@@ -206,7 +206,7 @@ struct sieve_ctx {
   template <typename F>
   void each_buf(F&& f) {
     DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
-                      &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
+                      &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &b_items, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
                       &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl, &logpat};
     for (DevBuf* b : bufs) f(*b);
     for (auto& b : pat) f(b);
@@ -1402,10 +1402,10 @@ uint64_t window_cap(const Window& w, uint64_t med_lim) {
 
 template <typename E>
 void launch_tile_batch(uint32_t L, uint32_t grid, hipStream_t s, const sv::BatchReq* rq, uint32_t nreq, uint32_t nitems,
-                       uint32_t run, uint32_t* queue, const uint32_t* P, const uint32_t* xpat, const void* bucket,
+                       const uint2* items, uint32_t* queue, const uint32_t* P, const uint32_t* xpat, const void* bucket,
                        const uint32_t* bstart, uint32_t b, uint32_t cap, uint32_t l, uint32_t* tcnt) {
-#define SV_TB(LL)                                                                                                  \
-  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, run, queue, P, xpat, bucket, bstart, b, cap, \
+#define SV_TB(LL)                                                                                                    \
+  sv::k_tile_batch<E, LL><<<grid, 1024, 0, s>>>(rq, nreq, nitems, items, queue, P, xpat, bucket, bstart, b, cap, \
                                                 l, tcnt)
   switch (L) {
     case 13: SV_TB(13); break;
@@ -1447,20 +1447,31 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   uint32_t items = 0, gbins = 0, tcnt = 0, seg_tot = 0, max_rbins = 1;
   const uint32_t* xpat = nullptr;
   const bool seg_long = L < l;
-  // tiles per work item: runs of kBatchRun carry offsets from tile to tile, but a
-  // batch with few tiles per resident workgroup takes shorter runs, so that its
-  // tiles spread over the device instead of queueing behind each other
+  // work items: runs of consecutive tiles of one request carry offsets from tile to
+  // tile (a run's first tile computes every first hit), so early items are long;
+  // the queue is taken in order and an item's length shrinks with the tiles still
+  // to be claimed (remaining / (2 x resident workgroups), at most kBatchRunMax), so
+  // the last items are single tiles and the workgroups finish together
   uint64_t all_tiles = 0;
   for (const Window& X : W) all_tiles += (X.lbits + (1ull << L) - 1) >> L;
   const uint64_t resident = (uint64_t)c->ncu * tiles_per_cu(L);
-  const uint32_t run = all_tiles >= 4 * resident ? kBatchRun : (all_tiles >= 2 * resident ? 2u : 1u);
+  c->h_items.clear();
+  uint64_t remaining = all_tiles;
   for (uint32_t w = 0; w < nw; ++w) {
     const Window& X = W[w];
     sv::BatchReq& q = c->h_req[w];
     memset(&q, 0, sizeof q);
     q.G0 = X.G0; q.B = X.B; q.lbits = X.lbits;
     q.ntiles = (X.lbits + (1u << L) - 1) >> L;
-    q.item0 = items; items += (q.ntiles + run - 1) / run;
+    q.item0 = items;
+    for (uint32_t t = 0; t < q.ntiles;) {
+      const uint32_t sz = (uint32_t)std::min<uint64_t>(
+          std::min<uint64_t>(kBatchRunMax, std::max<uint64_t>(1, remaining / (2 * resident))), q.ntiles - t);
+      c->h_items.push_back(make_uint2(w, t | (sz << 18)));     // t < 2^18 (2^31-bit windows, tiles >= 2^13)
+      t += sz;
+      remaining -= sz;
+    }
+    items = (uint32_t)c->h_items.size();
     q.psq = (uint32_t)std::min<uint64_t>(isqrt_u64(2 * X.G0 + 1), 0xFFFFFFFFull);
     const uint32_t* pat; uint32_t per, patw, pmask;
     STCHK(get_pattern(c, X.B, s, &pat, &per, &patw, &pmask));
@@ -1522,6 +1533,7 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   STCHK(c->b_blk.ensure(c->h_blk.size() * sizeof(uint2)));
   STCHK(c->b_seg0.ensure(nw * 4));
   STCHK(c->b_queue.ensure(64));
+  STCHK(c->b_items.ensure(c->h_items.size() * sizeof(uint2) + 64));
   if (seg_long) STCHK(c->b_tcnt.ensure((size_t)tcnt * 4 + 64));
   sv::BatchReq* dreq = c->b_req.as<sv::BatchReq>();
   for (sv::BatchReq& q : c->h_req) {
@@ -1538,8 +1550,9 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
     }
   const uint32_t njobs = (uint32_t)c->h_jobs.size();
   STCHK(pin_begin(c, pad256(nw * sizeof(sv::BatchReq)) + pad256(c->h_blk.size() * sizeof(uint2)) + pad256(nw * 4) +
-                         job_upload_bytes(c)));
+                         pad256(c->h_items.size() * sizeof(uint2)) + job_upload_bytes(c)));
   STCHK(upload(c, s, c->b_req.p, c->h_req.data(), nw * sizeof(sv::BatchReq)));
+  STCHK(upload(c, s, c->b_items.p, c->h_items.data(), c->h_items.size() * sizeof(uint2)));
   STCHK(upload(c, s, c->b_blk.p, c->h_blk.data(), c->h_blk.size() * sizeof(uint2)));
   STCHK(upload(c, s, c->b_seg0.p, c->h_seg0.data(), nw * 4));
   if (njobs) STCHK(upload_jobs(c, s));
@@ -1571,12 +1584,12 @@ int sieve_batch(sieve_ctx* ctx, const sieve_primes* pr, uint32_t l, const sieve_
   const uint32_t* bsp = njobs ? c->bstart.as<uint32_t>() : nullptr;
   if (esz == 2)
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, run, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
+      launch_tile_batch<uint16_t>(L, grid, s, dreq, nw, items, c->b_items.as<uint2>(), c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
                                   b, cap32, l, tc);
     }));
   else
     STCHK(launch(c, "k_tile_batch", s, [&] {
-      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, run, c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
+      launch_tile_batch<uint32_t>(L, grid, s, dreq, nw, items, c->b_items.as<uint2>(), c->b_queue.as<uint32_t>(), pr->P.as<uint32_t>(), xpat, bk, bsp,
                                   b, cap32, l, tc);
     }));
   if (seg_long)
