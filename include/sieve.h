@@ -150,9 +150,10 @@ int sieve_ctx_sieve_with(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uin
  * processing, here many intervals of Section 1.2.1 in one launch) ---
  * Sieves every request of reqs[0..nreq) (all with segment size 2^l) against the
  * one shared table pr: one offset kernel, one bucket fill and one persistent tile
- * kernel for the whole batch, whose workgroups take (request, run of up to four
- * consecutive tiles) work items from a device queue, longest first.  Each request's table and counts are the
- * same as sieve_init would give for it alone. */
+ * kernel for the whole batch, whose workgroups take (request, run of up to 16
+ * consecutive tiles) work items from a device queue in request order, the runs
+ * shortening as the queue drains (single tiles at its end).  Each request's table
+ * and counts are the same as sieve_init would give for it alone. */
 int sieve_batch(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, const sieve_req *reqs,
                 size_t nreq, const sieve_tune *tune, void *stream);
 /* --- device memory accounting (for admission control by a byte budget) ---
