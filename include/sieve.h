@@ -84,6 +84,13 @@ typedef enum {
  *   bin_log2    log2 of one bucket's width in bits, min(tile_log2,16)..tile_log2.
  *               Up to 16 a hit is stored as a 16-bit in-bucket offset, above 16
  *               as a 32-bit one.
+ *   sparse      large primes at least as long as a launch window (2^31 bits, or
+ *               the whole table when shorter) hit it at most once; with sparse = 2
+ *               they skip the bucket fill and each one's hit is OR-ed into the
+ *               finished table directly (then the counts are taken again); 1 keeps
+ *               them in the buckets; 0 (default) chooses by the expected hits per
+ *               such prime (direct when below 0.15).  sieve_ctx_sieve and sieve_init
+ *               only; batches keep every large prime in the buckets.
  */
 typedef struct {
     uint32_t tile_log2;
@@ -94,7 +101,8 @@ typedef struct {
     uint32_t bin_log2;
     uint32_t wheel_log2;
     uint32_t ranges;
-    uint32_t reserved[3];
+    uint32_t sparse;
+    uint32_t reserved[2];
 } sieve_tune;
 
 /* One interval of a batch: the interval of Section 1.2.1 with parameters

@@ -41,7 +41,7 @@ class Tune(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_uint32), ("medium_log2", ctypes.c_uint32),
                 ("wave_log2", ctypes.c_uint32), ("bins_log2", ctypes.c_uint32),
                 ("groups", ctypes.c_uint32), ("bin_log2", ctypes.c_uint32), ("wheel_log2", ctypes.c_uint32),
-                ("ranges", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("ranges", ctypes.c_uint32), ("sparse", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class Req(ctypes.Structure):

@@ -116,7 +116,7 @@ uint64_t isqrt_u64(uint64_t x) {
 }
 
 struct Resolved {
-  uint32_t L, Mlog, Wlog, Blog, binslog, groups, b, R;
+  uint32_t L, Mlog, Wlog, Blog, binslog, groups, b, R, sparse;
 };
 
 int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
@@ -139,6 +139,8 @@ int resolve_tune(uint32_t l, const sieve_tune* t, Resolved* r) {
   r->groups = t->groups ? t->groups : 2048;
   if (r->groups < 64 || r->groups > 4096) return SIEVE_E_ARG;
   if (r->R) r->groups -= r->groups % r->R;
+  r->sparse = t->sparse;
+  if (r->sparse > 2) return SIEVE_E_ARG;
   return SIEVE_OK;
 }
 
@@ -684,12 +686,30 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   const uint32_t L = R.L;
   const uint64_t wave_lim = 1ull << R.Wlog, wheel_lim = 1ull << R.Blog, med_lim = 1ull << R.Mlog;
   const uint64_t tab_ub = std::min<uint64_t>(pi_upper(B), pi_upper(pr->B));
+  // sparse large primes: p at least the launch window length (at most one hit per
+  // window), taken by k_sparse_hits after the tile kernel instead of the buckets when
+  // they have few hits: expected hits per such prime ~ NB ln(ln B / ln lim) / (primes
+  // in [lim, B]), direct below 0.15 (measured: walking a prime through the count and
+  // scatter passes costs about as much as 0.2 atomic ORs into the table, which stay
+  // coherent across the XCDs)
+  const uint64_t sparse_lim = std::max<uint64_t>(med_lim, std::min<uint64_t>(NB, kLaunchBits));
+  bool sparse = false;
+  if (!wide && R.sparse != 1 && sparse_lim > med_lim && B >= sparse_lim) {
+    if (R.sparse == 2) {
+      sparse = true;
+    } else if ((double)B >= 2.0 * (double)sparse_lim) {
+      const double np_sp = (double)B / std::log((double)B) - (double)sparse_lim / std::log((double)sparse_lim);
+      const double hits = (double)NB * std::log(std::log((double)B) / std::log((double)sparse_lim));
+      sparse = hits < 0.15 * np_sp;
+    }
+  }
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
     sv::k_plan<<<1, 64, 0, s>>>(pr->P.as<uint32_t>(), pr->cnt.as<uint32_t>(), B, use_xpat(B, L, l) ? 53 : 17, wave_lim,
-                               wheel_lim, med_lim, 1ull << (L - 3), (uint32_t)tab_ub, plan);
+                               wheel_lim, med_lim, 1ull << (L - 3), (uint32_t)tab_ub, plan, sparse ? sparse_lim : ~0ull);
   }));
+  const uint64_t B_dense = sparse ? sparse_lim - 1 : B;          // the bucket fill's primes end there
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
   STCHK(c->Q0.ensure(med_ub * 8 + 64));
   const bool large = B >= med_lim;
@@ -757,7 +777,7 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   uint64_t hg_max = 0, cap = 0, pad_max = 0;
   uint32_t nbins_max = 0;
   if (large) {
-    const double rs = recip_sum_upper((double)med_lim, (double)B);
+    const double rs = recip_sum_upper((double)med_lim, (double)B_dense);
     cap = (uint64_t)(1.02 * rs * (double)std::min<uint64_t>(chunk_max, NB)) + nL_ub + 4096;
     if (cap >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
   }
@@ -776,8 +796,9 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
         const uint32_t* oin = c->OFF.as<uint32_t>() + (size_t)off_cur * nL_ub;
         uint32_t* oout = c->OFF.as<uint32_t>() + (size_t)(1 - off_cur) * nL_ub;
         const size_t jb = c->h_jobs.size(), cjb = c->h_cjobs.size();
-        chunk_jobs(ch.nbins, (uint32_t)ch.cbits, b, R.R, R.groups, (double)med_lim, (double)B, pr->P.as<uint32_t>(),
-                   plan, oin, oout, 0, &c->h_jobs, &c->h_blk2job, &c->h_cjobs, &c->h_cblk2job, &c->h_thr, &hg);
+        chunk_jobs(ch.nbins, (uint32_t)ch.cbits, b, R.R, R.groups, (double)med_lim, (double)B_dense,
+                   pr->P.as<uint32_t>(), plan, oin, oout, 0, &c->h_jobs, &c->h_blk2job, &c->h_cjobs, &c->h_cblk2job,
+                   &c->h_thr, &hg);
         for (size_t k = jb; k < c->h_jobs.size(); ++k) {   // block numbers and job indices relative to the chunk
           c->h_jobs[k].block0 -= ch.b0;
           ch.max_rbins = std::max(ch.max_rbins, c->h_jobs[k].rbins);
@@ -857,6 +878,18 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint16_t>(c, L, s, ta); }));
     else
       STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(c, L, s, ta); }));
+    if (sparse && (&ch == &chunks.back() || (&ch + 1)->ls != ch.ls)) {
+      // the window is written: the sparse primes' hits, then its counts again
+      uint32_t* Sw = S + (ch.ls >> 5);
+      STCHK(launch(c, "k_sparse_hits", s, [&] {
+        sv::k_sparse_hits<<<(uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), 256, 0, s>>>(
+            pr->P.as<uint32_t>(), plan, G0, ch.lbits, Sw);
+      }));
+      const uint32_t nseg = (uint32_t)(ch.lbits >> l);
+      STCHK(launch(c, "k_recount", s, [&] {
+        sv::k_recount<<<l >= 13 ? nseg : (nseg + 255) / 256, 256, 0, s>>>(Sw, l, nseg, counts + (ch.ls >> l));
+      }));
+    }
   }
   return SIEVE_OK;
 }

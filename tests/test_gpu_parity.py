@@ -65,6 +65,23 @@ def test_near_2_64_bucket_path():
                tune={"tile_log2": 17, "medium_log2": 14, "bins_log2": 8, "bin_log2": 17, "groups": 96})
 
 
+@pytest.mark.parametrize("case", [
+    (20, 2**43 - 4, 3, 10**7),               # near 2^64
+    (18, 12345, 10, 5 * 10**6),              # every sparse prime starts past v (p^2 rule)
+    (16, 0, 64, 10**7),                      # from the number 1
+    (20, (10**15) >> 21, 4, 2 * 10**7),
+    (20, (10**12) >> 21, 40, 2**31 + 11),    # the largest bound class
+])
+def test_sparse_large_primes_direct(case):
+    # large primes at least as long as the table take the direct path (one hit at
+    # most, OR-ed after the tile kernel, counts taken again), forced on; also with
+    # tiles shorter than the segments (per-tile count atomics, then the recount)
+    l, f, n, B = case
+    check_case(l, f, n, B, tune={"sparse": 2})
+    check_case(l, f, n, B, tune={"sparse": 2, "tile_log2": 15})
+    check_case(l, f, n, B, tune={"sparse": 1})
+
+
 @pytest.mark.parametrize("groups", [1024, 4096])
 def test_bucket_fill_workgroup_counts(groups):
     # the bucket-fill workgroup counts the batch autotuner may pick, on the plain path
