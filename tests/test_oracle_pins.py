@@ -232,8 +232,8 @@ def test_prime_table_goldens_match_published_pi():
     g = json.load(open(os.path.join(HERE, "golden", "primes_4294967295.json")))
     assert g["count"] + 1 == pub[4294967296] and g["max"] == 4294967291
     # 2133783848 lies below 2^31: its count is at most pi(2^31) - 1 and the table is
-    # the prefix of the 2^32 one (checked on the GPU); the count is the survey's
-    # independent cross-check value
+    # the prefix of the 2^32 one (checked on the GPU); 104459685 = pi(2133783848) - 1
+    # was counted independently of this oracle
     g2 = json.load(open(os.path.join(HERE, "golden", "primes_2133783848.json")))
     assert g2["count"] == 104459685 and g2["count"] + 1 <= pub[2147483648]
 
