@@ -85,12 +85,12 @@ typedef enum {
  *               Up to 16 a hit is stored as a 16-bit in-bucket offset, above 16
  *               as a 32-bit one.
  *   sparse      large primes at least as long as a launch window (2^31 bits, or
- *               the whole table when shorter) hit it at most once; with sparse = 2
- *               they skip the bucket fill and each one's hit is OR-ed into the
- *               finished table directly (then the counts are taken again); 1 keeps
- *               them in the buckets; 0 (default) chooses by the expected hits per
- *               such prime (direct when below 0.15).  sieve_ctx_sieve and sieve_init
- *               only; batches keep every large prime in the buckets.
+ *               the whole table when shorter) hit it at most once.  0 (default)
+ *               or 2: they skip the bucket fill; after the tile kernel has
+ *               written the window their hits are computed, counting-sorted by
+ *               table range and OR-ed in (then the counts are taken again).  1
+ *               keeps them in the buckets.  sieve_ctx_sieve and sieve_init only;
+ *               batches keep every large prime in the buckets.
  */
 typedef struct {
     uint32_t tile_log2;

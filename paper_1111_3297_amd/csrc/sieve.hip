@@ -183,6 +183,7 @@ struct sieve_ctx {
   DevBuf gb_best, gb_k;   // Goldbach check: packed per-segment maxima, prime count
   DevBuf wsl;             // intervals beyond 2^64: a sieved slice of the primes above 2^32
   DevBuf logpat;          // log-add sieve: weights of 3..13 over one period
+  DevBuf spE, spH;        // sparse large primes: sorted hits per collecting workgroup, bin headers
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk, h_items;
   std::vector<uint32_t> h_seg0;
@@ -209,7 +210,7 @@ struct sieve_ctx {
   void each_buf(F&& f) {
     DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
                       &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &b_items, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
-                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl, &logpat};
+                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl, &logpat, &spE, &spH};
     for (DevBuf* b : bufs) f(*b);
     for (auto& b : pat) f(b);
   }
@@ -388,7 +389,8 @@ int set_lds_limits() {
     // 8 KB); the scatter's stages and counters use at most 152 KB
     const int lim = kScatterLds;
     const void* fns[] = {(const void*)sv::k_bucket_count2, (const void*)sv::k_bucket_scatter2<uint16_t>,
-                         (const void*)sv::k_bucket_scatter2<uint32_t>, (const void*)sv::k_bucket_scatter2<uint32_t, true>};
+                         (const void*)sv::k_bucket_scatter2<uint32_t>, (const void*)sv::k_bucket_scatter2<uint32_t, true>,
+                         (const void*)sv::k_sparse_apply};
     for (const void* f : fns)
       if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) rc = SIEVE_E_HIP;
   });
@@ -676,6 +678,14 @@ size_t job_upload_bytes(const sieve_ctx* c) {
          pad256(c->h_thr.size() * 4);
 }
 
+// Bin size of the sparse primes' sort for a window of lbits bits: about 256 bins, of
+// 2^15 .. 2^20 bits (the apply step holds one bin in LDS).
+uint32_t sp_binlog(uint64_t lbits) {
+  uint32_t lg = 0;
+  while ((1ull << lg) < lbits) ++lg;
+  return std::min<uint32_t>(20, std::max<uint32_t>(15, lg > 8 ? lg - 8 : 0));
+}
+
 // The sieve proper for one request (l, F, NB) with the table pr and bound B.
 // wide (two words, lo then hi), when given, is the true 128-bit start F of an
 // interval beyond 2^64: the first offsets come from it, every p^2 start rule is off
@@ -687,22 +697,11 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   const uint64_t wave_lim = 1ull << R.Wlog, wheel_lim = 1ull << R.Blog, med_lim = 1ull << R.Mlog;
   const uint64_t tab_ub = std::min<uint64_t>(pi_upper(B), pi_upper(pr->B));
   // sparse large primes: p at least the launch window length (at most one hit per
-  // window), taken by k_sparse_hits after the tile kernel instead of the buckets when
-  // they have few hits: expected hits per such prime ~ NB ln(ln B / ln lim) / (primes
-  // in [lim, B]), direct below 0.15 (measured: walking a prime through the count and
-  // scatter passes costs about as much as 0.2 atomic ORs into the table, which stay
-  // coherent across the XCDs)
+  // window), taken by k_sparse_collect / k_sparse_apply after the tile kernel instead
+  // of the buckets unless the tuning turns that off (the bucket path computes the same
+  // first offsets and then walks every prime twice more)
   const uint64_t sparse_lim = std::max<uint64_t>(med_lim, std::min<uint64_t>(NB, kLaunchBits));
-  bool sparse = false;
-  if (!wide && R.sparse != 1 && sparse_lim > med_lim && B >= sparse_lim) {
-    if (R.sparse == 2) {
-      sparse = true;
-    } else if ((double)B >= 2.0 * (double)sparse_lim) {
-      const double np_sp = (double)B / std::log((double)B) - (double)sparse_lim / std::log((double)sparse_lim);
-      const double hits = (double)NB * std::log(std::log((double)B) / std::log((double)sparse_lim));
-      sparse = hits < 0.15 * np_sp;
-    }
-  }
+  const bool sparse = !wide && R.sparse != 1 && sparse_lim > med_lim && B >= sparse_lim;
   STCHK(c->plan.ensure(sizeof(sv::Plan) * 2));
   sv::Plan* plan = c->plan.as<sv::Plan>();
   STCHK(launch(c, "k_plan", s, [&] {
@@ -713,7 +712,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
   const uint64_t med_ub = std::min<uint64_t>(tab_ub, pi_upper(med_lim));
   STCHK(c->Q0.ensure(med_ub * 8 + 64));
   const bool large = B >= med_lim;
-  const uint64_t nL_ub = large ? tab_ub : 0;
+  // bucketed primes: indices iM .. iS, and iS <= pi(sparse_lim - 1) when sparse
+  const uint64_t nL_ub = large ? (sparse ? std::min<uint64_t>(tab_ub, pi_upper(sparse_lim)) : tab_ub) : 0;
   if (large) STCHK(c->OFF.ensure(2 * nL_ub * 4 + 64));           // in / out halves
   const uint32_t* pat; uint32_t per, patw, pmask;
   STCHK(get_pattern(c, B, s, &pat, &per, &patw, &pmask));
@@ -826,6 +826,24 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     STCHK(upload_jobs(c, s));
     STCHK(pin_end(c, s));
   }
+  // sparse primes: at most tab_ub - (pi(sparse_lim - 1) - 1) of them, with
+  // pi(x) > x / ln x for x >= 17 (Rosser and Schoenfeld)
+  uint32_t sp_nwg = 0;
+  if (sparse) {
+    const double x = (double)(sparse_lim - 1);
+    const uint64_t below = (uint64_t)(x / std::log(x));
+    const uint64_t nsp_ub = tab_ub > below ? tab_ub - below + 2 : 2;
+    const uint64_t nwg = (nsp_ub + 8 * sv::kSpK - 1) / (8 * sv::kSpK) * 8;   // a multiple of the XCD count
+    if (nwg * sv::kSpK >= 0xFFFFFFFFull) return SIEVE_E_NOMEM;
+    sp_nwg = (uint32_t)nwg;
+    uint64_t hdr_words = 0;
+    for (uint64_t ls = 0; ls < NB; ls += kLaunchBits) {
+      const uint64_t lb = std::min<uint64_t>(kLaunchBits, NB - ls);
+      hdr_words = std::max<uint64_t>(hdr_words, ((lb + (1ull << sp_binlog(lb)) - 1) >> sp_binlog(lb)) * nwg);
+    }
+    STCHK(c->spE.ensure(nwg * sv::kSpK * 4));
+    STCHK(c->spH.ensure(hdr_words * 4 + 64));
+  }
   STCHK(ensure_err(c, s));
   const bool count_atomic = L < l;
   if (count_atomic) {
@@ -879,11 +897,19 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     else
       STCHK(launch(c, "k_tile", s, [&] { launch_tile<uint32_t>(c, L, s, ta); }));
     if (sparse && (&ch == &chunks.back() || (&ch + 1)->ls != ch.ls)) {
-      // the window is written: the sparse primes' hits, then its counts again
+      // the window is written: the sparse primes' hits, sorted by bin, OR-ed in; then
+      // its counts again
       uint32_t* Sw = S + (ch.ls >> 5);
-      STCHK(launch(c, "k_sparse_hits", s, [&] {
-        sv::k_sparse_hits<<<(uint32_t)((tab_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer)), 256, 0, s>>>(
-            pr->P.as<uint32_t>(), plan, G0, ch.lbits, Sw);
+      const uint32_t binlog = sp_binlog(ch.lbits);
+      const uint32_t nbins = (uint32_t)((ch.lbits + (1ull << binlog) - 1) >> binlog);
+      STCHK(launch(c, "k_sparse_collect", s, [&] {
+        sv::k_sparse_collect<<<sp_nwg, sv::kSpThreads, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits, binlog,
+                                                               nbins, sp_nwg, c->spE.as<uint32_t>(),
+                                                               c->spH.as<uint32_t>(), c->err.as<uint32_t>());
+      }));
+      STCHK(launch(c, "k_sparse_apply", s, [&] {
+        sv::k_sparse_apply<<<nbins, sv::kSpApplyThreads, (1u << binlog) / 8, s>>>(
+            c->spE.as<uint32_t>(), c->spH.as<uint32_t>(), sp_nwg, binlog, ch.lbits, Sw);
       }));
       const uint32_t nseg = (uint32_t)(ch.lbits >> l);
       STCHK(launch(c, "k_recount", s, [&] {

@@ -27,6 +27,30 @@ def request_bytes(l, n):
     return (n << l) // 8 + 4 * n
 
 
+# Allocator rounding that an upper bound of the device memory a request adds must
+# cover, on top of the exact sizes: PyTorch's caching allocator takes a block of
+# 2 MiB for a request of at most 1 MiB, 20 MiB below 10 MiB and whole 2 MiB units
+# above; a library scratch buffer may end in a partly used 2 MiB page.
+TORCH_SMALL, TORCH_MID, TORCH_UNIT = 2 << 20, 20 << 20, 2 << 20
+LIB_BUFFERS, LIB_PAGE = 24, 2 << 20
+
+
+def torch_block_bytes(nbytes):
+    """Device bytes PyTorch's caching allocator may take for one tensor of nbytes."""
+    if nbytes <= (1 << 20):
+        return TORCH_SMALL
+    if nbytes < (10 << 20):
+        return TORCH_MID
+    return -(-nbytes // TORCH_UNIT) * TORCH_UNIT
+
+
+def request_bytes_bound(l, n, scratch):
+    """Upper bound of the device bytes admitting a request adds: its table and counts
+    as PyTorch allocates them, plus the library's planned scratch and a page of
+    rounding for each of its buffers."""
+    return torch_block_bytes((n << l) // 8) + torch_block_bytes(4 * n) + scratch + LIB_BUFFERS * LIB_PAGE
+
+
 class GpuExecutor:
     """Runs groups of requests with sieve_batch (a group of one with the plain
     per-interval call when single_plain, which has less fixed cost), one context
@@ -53,7 +77,8 @@ class GpuExecutor:
     def request_bytes(self, r):
         """Upper bound of the device bytes admitting r can add: its table and counts
         plus the scratch a fresh context would need for it (the planning pass of the
-        library, for the batched and, when used, the plain call)."""
+        library, for the batched and, when used, the plain call), with the
+        allocators' rounding (request_bytes_bound)."""
         key = (r.f, r.n, r.B)
         c = self._cost.get(key)
         if c is None:
@@ -61,7 +86,7 @@ class GpuExecutor:
             sc = ctx.batch_scratch_bytes(self.primes, self.l, [(r.f, r.n, r.B)], tune=self.tune)
             if self.single_plain:
                 sc = max(sc, ctx.sieve_scratch_bytes(self.l, r.f, r.n, r.B, tune=self.tune, primes=self.primes))
-            c = request_bytes(self.l, r.n) + sc
+            c = request_bytes_bound(self.l, r.n, sc)
             self._cost[key] = c
         return c
 

@@ -71,15 +71,52 @@ def test_near_2_64_bucket_path():
     (16, 0, 64, 10**7),                      # from the number 1
     (20, (10**15) >> 21, 4, 2 * 10**7),
     (20, (10**12) >> 21, 40, 2**31 + 11),    # the largest bound class
+    (13, (10**15) >> 14, 385, 2 * 10**7),    # 97 bins of the hit sort, the last one partial
 ])
 def test_sparse_large_primes_direct(case):
-    # large primes at least as long as the table take the direct path (one hit at
-    # most, OR-ed after the tile kernel, counts taken again), forced on; also with
-    # tiles shorter than the segments (per-tile count atomics, then the recount)
+    # large primes at least as long as the table take the sparse path (one hit at
+    # most, sorted by bin and OR-ed in after the tile kernel, counts taken again);
+    # also with tiles shorter than the segments (per-tile count atomics, then the
+    # recount), and turned off (the bucket path)
     l, f, n, B = case
     check_case(l, f, n, B, tune={"sparse": 2})
     check_case(l, f, n, B, tune={"sparse": 2, "tile_log2": 15})
     check_case(l, f, n, B, tune={"sparse": 1})
+
+
+def test_sparse_path_wide_window_golden():
+    # a 2^30-bit table from 2^62 with every prime below 2^32: the sparse primes
+    # (2^30 <= p < 2^32, about 0.46 hits each) take 1024 bins of 2^20 bits; the
+    # sparse path and the bucket path both against the oracle's golden (counts of
+    # every segment and the SHA-256 of the table)
+    import torch
+    from paper_1111_3297_amd import api
+    g = _golden("interval_2p62_w30")
+    l, f, n, B = g["l"], g["f"], g["n"], g["B"]
+    pr = api.Primes(B)
+    for tune in ({"sparse": 2}, {"sparse": 1}):
+        say("sparse wide window", l, f, n, B, tune)
+        S, c = gpu_sieve(l, f, n, B, tune=tune, primes=pr)
+        assert [int(x) for x in c] == g["counts"], tune
+        assert sha256_words(S) == g["S_sha256"], tune
+    del pr
+    torch.cuda.empty_cache()
+
+
+def test_planned_scratch_equals_held_scratch():
+    # the planning pass (sieve_sieve_scratch_bytes) gives exactly the device bytes a
+    # fresh context holds after the call: the sparse path, the bucket path, medium
+    # primes only
+    from paper_1111_3297_amd import api
+    for (l, f, n, B, tune) in [(20, 2**43 - 65, 64, 2**32 - 1, None), (20, 2**43 - 65, 64, 2**32 - 1, {"sparse": 1}),
+                               (20, (10**12) >> 21, 40, 2**31 + 11, None), (20, (10**14) >> 21, 8, 10**6, None)]:
+        pr = api.Primes(B)
+        ctx = api.Context()
+        planned = ctx.sieve_scratch_bytes(l, f, n, B, tune=tune, primes=pr)
+        S, c = api.alloc(l, n)
+        ctx.sieve(l, f, n, B, S, c, tune=tune, primes=pr)
+        ctx.check_device_errors()
+        assert ctx.scratch_bytes() == planned, (l, f, n, B, tune)
 
 
 @pytest.mark.parametrize("groups", [1024, 4096])

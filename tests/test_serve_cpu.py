@@ -152,3 +152,16 @@ def test_latency_counts_from_scheduled_arrival_when_slots_are_full():
     # one slot, one request per group: completions at 0.1, 0.2, 0.3 s after arrival 0
     assert abs(st["max_ms"] - 300.0) < 1.0
     assert abs(st["p50_ms"] - 200.0) < 1.0
+
+
+def test_request_bound_covers_allocator_rounding():
+    # PyTorch's caching allocator: 2 MiB blocks up to 1 MiB, 20 MiB below 10 MiB,
+    # whole 2 MiB units above; the bound adds a page per library buffer
+    assert serve.torch_block_bytes(512) == 2 << 20
+    assert serve.torch_block_bytes((1 << 20) + 1) == 20 << 20
+    assert serve.torch_block_bytes(16 << 20) == 16 << 20
+    assert serve.torch_block_bytes((16 << 20) + 1) == 18 << 20
+    for l, n in [(10, 1), (20, 3), (20, 128), (16, 4096)]:
+        exact = serve.request_bytes(l, n)
+        b = serve.request_bytes_bound(l, n, 12345)
+        assert b >= exact + 12345 + serve.LIB_BUFFERS * serve.LIB_PAGE
