@@ -902,10 +902,18 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
       uint32_t* Sw = S + (ch.ls >> 5);
       const uint32_t binlog = sp_binlog(ch.lbits);
       const uint32_t nbins = (uint32_t)((ch.lbits + (1ull << binlog) - 1) >> binlog);
+      // the p^2 start rule can move a sparse prime's hit only if p^2 > u, i.e. p >
+      // isqrt(2 G0 + 1) for some prime p >= sparse_lim of the table (p <= B)
+      const bool sq = isqrt_u64(2 * G0 + 1) < B;
       STCHK(launch(c, "k_sparse_collect", s, [&] {
-        sv::k_sparse_collect<<<sp_nwg, sv::kSpThreads, 0, s>>>(pr->P.as<uint32_t>(), plan, G0, ch.lbits, binlog,
-                                                               nbins, sp_nwg, c->spE.as<uint32_t>(),
-                                                               c->spH.as<uint32_t>(), c->err.as<uint32_t>());
+        if (sq)
+          sv::k_sparse_collect<true><<<sp_nwg, sv::kSpThreads, 0, s>>>(
+              pr->P.as<uint32_t>(), plan, G0, ch.lbits, binlog, nbins, sp_nwg, c->spE.as<uint32_t>(),
+              c->spH.as<uint32_t>(), c->err.as<uint32_t>());
+        else
+          sv::k_sparse_collect<false><<<sp_nwg, sv::kSpThreads, 0, s>>>(
+              pr->P.as<uint32_t>(), plan, G0, ch.lbits, binlog, nbins, sp_nwg, c->spE.as<uint32_t>(),
+              c->spH.as<uint32_t>(), c->err.as<uint32_t>());
       }));
       STCHK(launch(c, "k_sparse_apply", s, [&] {
         sv::k_sparse_apply<<<nbins, sv::kSpApplyThreads, (1u << binlog) / 8, s>>>(
