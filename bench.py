@@ -74,6 +74,30 @@ def marks_executed(primes, u, v, tile_log2=20, first_med=53):
     return float(np.where(wheel, w, a).sum())
 
 
+SPARSE_BYTES_PER_PRIME = 4                  # a sparse large prime is read once (its hit computed from it)
+SPARSE_BYTES_PER_HIT = 4                    # and its hit, if any, written once as a table index
+LAUNCH_BITS = 1 << 31                       # a launch window of the table
+
+
+def sparse_counts(primes, l, f, n):
+    """Sparse large primes of a single-window table (p at least the table length,
+    at most one hit each) and how many of them hit it: the first odd multiple of p
+    at or above max(u, p^2) (Lemma 1, Section 1.4) below v."""
+    import numpy as np
+    nb = n << l
+    if nb > LAUNCH_BITS:
+        return 0, 0
+    p = primes[primes >= nb].astype(np.int64)
+    if p.size == 0:
+        return 0, 0
+    G0 = f << l
+    h = (p - 1) // 2
+    j = np.mod(h - np.mod(G0, p), p)
+    gsq = (p * p - 1) // 2
+    j = np.where(gsq > G0 + j, gsq - G0, j)
+    return int(p.size), int(np.count_nonzero(j < nb))
+
+
 def large_hits(primes, u, v, med_lim):
     import numpy as np
     p = primes[primes >= med_lim].astype(np.float64)
@@ -711,13 +735,25 @@ def plain_rooflines(rec, rates):
     dom = max(ks, key=lambda k: ks[k]["total_ms"])
     out = {}
     if "k_bucket_scatter" in ks:
-        hits = large_hits(primes, u, v, 1 << 20)
+        # the bucketed primes: from the medium bound on, up to the sparse ones when
+        # those take their own path (p at least the table length)
+        bucketed = primes[primes < (rec["n"] << rec["l"])] if "k_sparse_collect" in ks else primes
+        hits = large_hits(bucketed, u, v, 1 << 20)
         kt = ks["k_bucket_scatter"]
         per_ms = kt["total_ms"] / kt["launches_per_step"]
         out["k_bucket_scatter"] = roofline_hbm("k_bucket_scatter", BUCKET_BYTES_PER_HIT * hits / kt["launches_per_step"],
                                                per_ms, traffic_from_profile(rec["name"], "k_bucket_scatter"),
                                                "%d bytes per large-prime hit (%.4g hits per step)"
                                                % (BUCKET_BYTES_PER_HIT, hits))
+    if "k_sparse_collect" in ks:
+        nsp, hits = sparse_counts(primes, rec["l"], rec["f"], rec["n"])
+        kt = ks["k_sparse_collect"]
+        per_ms = kt["total_ms"] / kt["launches_per_step"]
+        out["k_sparse_collect"] = roofline_hbm(
+            "k_sparse_collect", (SPARSE_BYTES_PER_PRIME * nsp + SPARSE_BYTES_PER_HIT * hits) / kt["launches_per_step"],
+            per_ms, traffic_from_profile(rec["name"], "k_sparse_collect"),
+            "%d bytes per sparse large prime (%d) and %d per hit (%d)"
+            % (SPARSE_BYTES_PER_PRIME, nsp, SPARSE_BYTES_PER_HIT, hits))
     kt = ks.get("k_tile")
     if kt:
         per_ms = kt["total_ms"] / kt["launches_per_step"]
@@ -734,7 +770,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batch_1234", help="batch_1234 (headline) or a plain interval workload")
-    ap.add_argument("--also", default="interval_1e12,interval_2p60", help="comma list of plain workloads to report")
+    ap.add_argument("--also", default="interval_1e12,interval_2p60,serve_req6388",
+                    help="comma list of plain workloads to report")
     ap.add_argument("--latency-steps", type=int, default=200, help="calls of the small interval for launch latency")
     ap.add_argument("--goldbach-steps", type=int, default=10, help="timed Goldbach checks of the 1e12 table (0: skip)")
     ap.add_argument("--logsieve-steps", type=int, default=10, help="timed log-add sieves of the 1e12 interval (0: skip)")

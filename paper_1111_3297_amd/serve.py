@@ -52,9 +52,11 @@ def request_bytes_bound(l, n, scratch):
 
 
 class GpuExecutor:
-    """Runs groups of requests with sieve_batch (a group of one with the plain
-    per-interval call when single_plain, which has less fixed cost), one context
-    and stream per slot."""
+    """Runs groups of requests with sieve_batch, one context and stream per slot.
+    With single_plain, a group of one runs as the plain per-interval call (less
+    fixed cost), and so do the requests of a larger group that have sparse large
+    primes (sparse_plain), one after the other on the slot's stream before the
+    batch of the rest."""
 
     def __init__(self, primes, l, slots=3, tune=None, keep_outputs=False, single_plain=True):
         import torch
@@ -116,12 +118,27 @@ class GpuExecutor:
                 s["ctx"].trim()
         self.torch.cuda.empty_cache()
 
+    def sparse_plain(self, n, B):
+        """Whether a request has sparse large primes (p at least its table length of
+        n 2^l bits, above the default medium bound 2^20): the plain call takes them
+        on a path of their own, which batches do not have."""
+        nb = n << self.l
+        return nb > (1 << 20) and B >= min(nb, 1 << 31)
+
     def _launch(self, slot, outs):
+        ctx, st = slot["ctx"], slot["stream"]
+        if self.single_plain:
+            # a group of one, and the requests with sparse large primes, as plain calls
+            one = len(outs) == 1
+            for (f, n, B, S, c) in outs:
+                if one or self.sparse_plain(n, B):
+                    ctx.sieve(self.l, f, n, B, S, c, tune=self.tune, stream=st, primes=self.primes)
+            outs = [o for o in outs if not (one or self.sparse_plain(o[1], o[2]))]
         if len(outs) == 1 and self.single_plain:
             f, n, B, S, c = outs[0]
-            slot["ctx"].sieve(self.l, f, n, B, S, c, tune=self.tune, stream=slot["stream"], primes=self.primes)
-        else:
-            slot["ctx"].batch(self.primes, self.l, outs, tune=self.tune, stream=slot["stream"])
+            ctx.sieve(self.l, f, n, B, S, c, tune=self.tune, stream=st, primes=self.primes)
+        elif outs:
+            ctx.batch(self.primes, self.l, outs, tune=self.tune, stream=st)
 
     def submit(self, reqs):
         torch = self.torch
@@ -168,8 +185,8 @@ class PlainExecutor(GpuExecutor):
         c = self._cost.get(key)
         if c is None:
             ctx = self.slots[0]["ctx"]
-            c = request_bytes(self.l, r.n) + ctx.sieve_scratch_bytes(self.l, r.f, r.n, r.B, tune=self.tune,
-                                                                      primes=self.primes)
+            c = request_bytes_bound(self.l, r.n, ctx.sieve_scratch_bytes(self.l, r.f, r.n, r.B, tune=self.tune,
+                                                                         primes=self.primes))
             self._cost[key] = c
         return c
 

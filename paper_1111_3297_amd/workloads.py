@@ -26,6 +26,8 @@ def plain_configs():
         "interval_1e12": (20, f12, 4096, math.isqrt(v)),     # 2^33 numbers centred at 1e12
         "interval_1e12_b6": (20, f12, 4096, 10**6),          # same interval, literal bound 10^6
         "interval_2p60": (20, 2**39 - 2048, 4096, 2**30),    # 2^33 numbers centred at 2^60
+        # the serving stream's request of largest bound: 2^28 numbers near 9.1e18
+        "serve_req6388": (20, 2171055560302, 128, 2133783848),
     }
 
 

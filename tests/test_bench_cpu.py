@@ -69,3 +69,23 @@ def test_log_adds_match_brute_force():
     for (u, v) in [(1, 20000), (99999, 130000), (10**9 + 1, 10**9 + 40000)]:
         want = sum(1 for p in P for N in range(u, v + 1) if N % 2 and N % p == 0)
         assert bench.log_adds(P, u, v) == want, (u, v)
+
+
+def test_sparse_counts_match_brute_force():
+    # sparse large primes (p at least the table length) and those of them with a
+    # hit: an odd multiple of p in [max(u, p^2), v]
+    P = _primes(40000)
+    P = P[P >= 3].astype(np.uint32)
+    for (l, f, n) in [(10, 12345, 4), (12, 0, 2), (11, 999, 3)]:
+        nb = n << l
+        u = (f << (l + 1)) + 1
+        v = u + 2 * (nb - 1)
+        sp = [int(p) for p in P if p >= nb]
+        hits = 0
+        for p in sp:
+            lo = max(u, p * p)
+            m = -(-lo // p)
+            if m % 2 == 0:
+                m += 1
+            hits += m * p <= v
+        assert bench.sparse_counts(P, l, f, n) == (len(sp), hits), (l, f, n)

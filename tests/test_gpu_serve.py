@@ -99,3 +99,22 @@ def test_admission_keeps_device_memory_within_a_binding_budget():
         c = res[r.rid]["counts"]
         assert [int(c.astype(np.int64).sum()), hashlib.sha256(c.astype("<u4").tobytes()).hexdigest()[:16]] == \
             g["requests"][r.rid][:2], r
+
+
+def test_group_with_sparse_request_matches_oracle():
+    # one group of light requests and the heavy requests 71 and 77 (sparse large
+    # primes: run as plain calls on the slot's stream before the batch of the rest),
+    # every table and count against the oracle's golden
+    from paper_1111_3297_amd import api, serve
+    g = _serve_golden()
+    l = 20
+    reqs = serve.serving_requests(l=l, limit_s=0.45)
+    by = {r.rid: r for r in reqs}
+    group = [by[k] for k in (70, 71, 72, 77, 78)]
+    pr = api.Primes(max(r.B for r in group))
+    ex = serve.GpuExecutor(pr, l, slots=1, keep_outputs=True)
+    assert [ex.sparse_plain(r.n, r.B) for r in group] == [False, True, False, True, False]
+    res = ex.finish(ex.submit(group))
+    for r in group:
+        got = _digest(res[r.rid]["S"], res[r.rid]["counts"])
+        assert list(got) == g["requests"][r.rid], (r, got)

@@ -165,3 +165,14 @@ def test_request_bound_covers_allocator_rounding():
         exact = serve.request_bytes(l, n)
         b = serve.request_bytes_bound(l, n, 12345)
         assert b >= exact + 12345 + serve.LIB_BUFFERS * serve.LIB_PAGE
+
+
+def test_sparse_plain_rule():
+    # sparse large primes exist when the table is longer than the medium bound 2^20
+    # and B reaches its length (capped at one 2^31-bit window)
+    class E:
+        l = 20
+    sp = lambda n, B: serve.GpuExecutor.sparse_plain(E, n, B)
+    assert not sp(1, 10**9)                 # 2^20 bits: every large prime is bucketed
+    assert sp(128, 2**27) and not sp(128, 2**27 - 1)
+    assert sp(4096, 2**31) and not sp(4096, 2**31 - 1)

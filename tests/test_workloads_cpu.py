@@ -14,6 +14,10 @@ def test_plain_configs():
     l, f, n, B = cfg["interval_2p60"]
     assert W.interval(l, f, n) == (2**60 - 2**32 + 1, 2**60 + 2**32) and B == 2**30
     assert W.interval(*cfg["interval_2p22"][:3]) == (1, 2**22)
+    # the serving stream's request of largest bound, as a plain workload
+    l, f, n, B = cfg["serve_req6388"]
+    t, f21, n21, kind = W.serving_stream(99, 200.0, 60.0)[6388]
+    assert (l, f, n) == (20, f21, n21) and B == math.isqrt(W.interval(l, f, n)[1]) == 2133783848
 
 
 def test_batch_fingerprint():
