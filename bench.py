@@ -87,15 +87,16 @@ def sparse_counts(primes, l, f, n):
     nb = n << l
     if nb > LAUNCH_BITS:
         return 0, 0
-    p = primes[primes >= nb].astype(np.int64)
+    p = primes[primes >= nb].astype(np.uint64)      # p < 2^32: p^2 fits 64 bits unsigned
     if p.size == 0:
         return 0, 0
-    G0 = f << l
-    h = (p - 1) // 2
-    j = np.mod(h - np.mod(G0, p), p)
-    gsq = (p * p - 1) // 2
+    G0 = np.uint64(f << l)
+    h = (p - np.uint64(1)) // np.uint64(2)
+    r = G0 % p
+    j = np.where(h >= r, h - r, h + (p - r))
+    gsq = (p * p - np.uint64(1)) // np.uint64(2)
     j = np.where(gsq > G0 + j, gsq - G0, j)
-    return int(p.size), int(np.count_nonzero(j < nb))
+    return int(p.size), int(np.count_nonzero(j < np.uint64(nb)))
 
 
 def large_hits(primes, u, v, med_lim):

@@ -17,8 +17,8 @@ Workloads (interval parameters of Section 1.2.1):
                      B = isqrt(v) = 2133783848
   interval_2p64_top: l=20, n=64 ending at v = 2^64 - 2^21, B = isqrt(v) = 2^32 - 1
   interval_2p62_w30: l=20, f=2^41 (u = 2^62 + 1), n=1024 (2^30 bits), B = 2^32 - 1,
-                     every 32-bit prime (those above isqrt(v) mark composites only):
-                     primes from 2^30 on hit the table at most once each
+                     every 32-bit prime: those from 2^30 on hit the table at most once
+                     each, those above 2^31 not at all (their squares lie past v)
   wide_2p66        : beyond 2^64 (128-bit f): l=16, f=2^49-128, n=128 ending at
                      v = 2^66, B = 2^33 = isqrt(v) (primes above 32 bits sieve)
   wide_b32         : l=14, f=2^90+12345, n=64, B = 2^32 - 1 (every 32-bit prime)

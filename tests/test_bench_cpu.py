@@ -89,3 +89,18 @@ def test_sparse_counts_match_brute_force():
                 m += 1
             hits += m * p <= v
         assert bench.sparse_counts(P, l, f, n) == (len(sp), hits), (l, f, n)
+    # the largest 32-bit primes (p^2 near 2^64) against tables near 2^62 and 2^64
+    big = np.array([4294967291, 4294967279, 4294967231, 4294967197, 4294967189, 4294967161, 3037000493,
+                    3037000453, 2147483647, 2147483629], dtype=np.uint32)
+    for (l, f, n) in [(20, 2**43 - 65, 64), (20, 2**41, 64), (16, 2**46 - 7, 3)]:
+        nb = n << l
+        u = (f << (l + 1)) + 1
+        v = u + 2 * (nb - 1)
+        hits = 0
+        for p in (int(x) for x in big):
+            lo = max(u, p * p)
+            m = -(-lo // p)
+            if m % 2 == 0:
+                m += 1
+            hits += m * p <= v
+        assert bench.sparse_counts(big, l, f, n) == (len(big), hits), (l, f, n)

@@ -86,7 +86,8 @@ def test_sparse_large_primes_direct(case):
 
 def test_sparse_path_wide_window_golden():
     # a 2^30-bit table from 2^62 with every prime below 2^32: the sparse primes
-    # (2^30 <= p < 2^32, about 0.46 hits each) take 1024 bins of 2^20 bits; the
+    # (2^30 <= p < 2^32; 1.49e8 of them with 3.52e7 hits, none from those above
+    # 2^31, whose squares lie past the table) take 1024 bins of 2^20 bits; the
     # sparse path and the bucket path both against the oracle's golden (counts of
     # every segment and the SHA-256 of the table)
     import torch
