@@ -683,7 +683,8 @@ def run_wide(steps, l=20, f=2**49, n=1024):
             "frac": nrem / (kw["total_ms"] * 1e-3) / peak,
             "per_call": {"remainders": nrem, "ms": kw["total_ms"], "launches": kw["launches_per_step"],
                          "what": "one 128-bit remainder per prime in (2^32, B] (%d fp64 operations each at "
-                                 "the peak), plus its hits OR-ed into the table" % ops}}
+                                 "the peak), plus its hit listed for the sort by table range (k_hits_sort and "
+                                 "k_sparse_apply, timed apart) or OR-ed into the table" % ops}}
     return {"workload": "prime table of the odd numbers 2^70 + 1 .. 2^70 + 2^31 (2^30 bits) with the odd "
                         "primes up to %d (128-bit start, sieving primes above 32 bits)" % B,
             "ms_per_call": ms, "p99_ms": _pct(lat, 0.99), "numbers_per_s": (v - u + 1) / (ms * 1e-3),

@@ -184,6 +184,7 @@ struct sieve_ctx {
   DevBuf wsl;             // intervals beyond 2^64: a sieved slice of the primes above 2^32
   DevBuf logpat;          // log-add sieve: weights of 3..13 over one period
   DevBuf spE, spH;        // sparse large primes: sorted hits per collecting workgroup, bin headers
+  DevBuf wH, wHc, wE, wHd;  // primes above 2^32: hit slots and counts, sorted regions, bin headers
   std::vector<sv::BatchReq> h_req;
   std::vector<uint2> h_blk, h_items;
   std::vector<uint32_t> h_seg0;
@@ -210,7 +211,8 @@ struct sieve_ctx {
   void each_buf(F&& f) {
     DevBuf* bufs[] = {&plan, &Q0, &OFF, &HG, &PS, &bstart, &bucket, &err, &gen_S, &gen_blk, &mb_sink,
                       &b_req, &b_blk, &b_seg0, &b_tcnt, &b_queue, &b_items, &jobs, &blk2job, &cjobs, &cblk2job, &thr,
-                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl, &logpat, &spE, &spH};
+                      &own.P, &own.cnt, &xpat, &gb_best, &gb_k, &wsl, &logpat, &spE, &spH,
+                      &wH, &wHc, &wE, &wHd};
     for (DevBuf* b : bufs) f(*b);
     for (auto& b : pat) f(b);
   }
@@ -1894,6 +1896,9 @@ constexpr uint64_t kSliceBits = 1ull << 30;       // odd numbers per slice
 // 3*5*7*...*47: the tile kernel reads the start of the interval only modulo the
 // pattern periods (divisors of 3*5*7*11*13 and of 17*19*23, 29*31*37, 41*43*47)
 constexpr uint64_t kProxyMod = 307444891294245705ull;
+constexpr uint32_t kWideHcap = 4096;        // hit slot of a k_wide_hits workgroup (list mode)
+constexpr double kWideListMin = 96.0;       // fewest expected hits per workgroup for the list mode
+constexpr double kWideSortHits = 7600.0;    // expected hits per sorting workgroup (sv::kSpK at most)
 
 int check_wide(uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B, uint64_t* Flo, uint64_t* Fhi,
                uint64_t* NB) {
@@ -1934,19 +1939,74 @@ extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_
     STCHK(c->wsl.ensure(need / 8 + (need >> kSliceLog) * 4 + 256));
     uint32_t* sl = c->wsl.as<uint32_t>();
     uint32_t* slc = sl + need / 32;
+    // The slices, and which of them list their hits for a sort by table range
+    // instead of OR-ing them in with atomics: tables of at most 2^31 bits (one hit
+    // per prime at most), and slices whose workgroups expect at least kWideListMin
+    // hits (65536 odd numbers, prime density 2 / ln p, hit probability NB / p at the
+    // slice's smallest p); G slots per sorting workgroup for about kWideSortHits hits.
+    struct Slice { uint64_t Fs, NBs; uint32_t nw, g, G, nsort; bool list; };
+    std::vector<Slice> slices;
+    uint32_t nregions = 0, gmax = 0;
     for (uint64_t Fs = k_lo; Fs <= k_hi; Fs += kSliceBits) {
-      const uint64_t NBs = std::min<uint64_t>(need, ((k_hi - Fs + 1 + (1ull << kSliceLog) - 1) >> kSliceLog) << kSliceLog);
+      Slice z;
+      z.Fs = Fs;
+      z.NBs = std::min<uint64_t>(need, ((k_hi - Fs + 1 + (1ull << kSliceLog) - 1) >> kSliceLog) << kSliceLog);
+      z.nw = (uint32_t)(z.NBs / 32);
+      z.g = (z.nw + 256 * sv::kWideRounds - 1) / (256 * sv::kWideRounds);
+      const double plo = 2.0 * (double)Fs + 1.0;
+      const double e = 256.0 * sv::kWideRounds * 32.0 * (2.0 / std::log(plo)) * std::min(1.0, (double)NB / plo);
+      z.list = NB <= kLaunchBits && e >= kWideListMin;
+      z.G = z.list ? (uint32_t)std::max(1.0, std::min<double>(sv::kHsMaxG, std::floor(kWideSortHits / e))) : 0;
+      z.nsort = z.list ? ((z.g + z.G - 1) / z.G + 7) / 8 * 8 : 0;
+      nregions += z.nsort;
+      if (z.list) gmax = std::max(gmax, z.g);
+      slices.push_back(z);
+    }
+    if ((uint64_t)nregions * sv::kSpK >= 0xFFFFFFFFull) {   // region offsets are 32-bit: atomics for all
+      for (Slice& z : slices) { z.list = false; z.G = z.nsort = 0; }
+      nregions = 0;
+    }
+    const uint32_t wbin = sp_binlog(NB);
+    const uint32_t wnbins = (uint32_t)((NB + (1ull << wbin) - 1) >> wbin);
+    if (nregions) {
+      STCHK(c->wH.ensure((size_t)gmax * kWideHcap * 4));
+      STCHK(c->wHc.ensure((size_t)gmax * 4 + 64));
+      STCHK(c->wE.ensure((size_t)nregions * sv::kSpK * 4));
+      STCHK(c->wHd.ensure((size_t)nregions * wnbins * 4 + 64));
+    }
+    uint32_t out0 = 0;
+    for (const Slice& z : slices) {
+      const uint64_t Fs = z.Fs, NBs = z.NBs;
       const uint64_t Bs = std::max<uint64_t>(3, isqrt_u64(2 * (Fs + NBs)));
       STCHK(run_sieve(c, &c->own, kSliceLog, Fs, NBs, Bs, sl, slc, Rs, s));
-      const uint32_t nw = (uint32_t)(NBs / 32);
+      const uint32_t nw = z.nw, g = z.g;
+      uint32_t* H = c->wH.as<uint32_t>();
+      uint32_t* Hc = c->wHc.as<uint32_t>();
       // remainder digits as wide as p < 2^(53-D) allows: 7, 8 or 11 steps
       STCHK(launch(c, "k_wide_hits", s, [&] {
-        const uint32_t g = (nw + 256 * sv::kWideRounds - 1) / (256 * sv::kWideRounds);
-        if (B <= (1ull << 33)) sv::k_wide_hits<20><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
-        else if (B <= (1ull << 36)) sv::k_wide_hits<17><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
-        else sv::k_wide_hits<12><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev);
+        if (z.list) {
+          if (B <= (1ull << 33)) sv::k_wide_hits<20, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, kWideHcap);
+          else if (B <= (1ull << 36)) sv::k_wide_hits<17, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, kWideHcap);
+          else sv::k_wide_hits<12, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, kWideHcap);
+        } else {
+          if (B <= (1ull << 33)) sv::k_wide_hits<20, false><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, nullptr, nullptr, 0);
+          else if (B <= (1ull << 36)) sv::k_wide_hits<17, false><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, nullptr, nullptr, 0);
+          else sv::k_wide_hits<12, false><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, nullptr, nullptr, 0);
+        }
       }));
+      if (z.list) {
+        STCHK(launch(c, "k_hits_sort", s, [&] {
+          sv::k_hits_sort<<<z.nsort, sv::kSpThreads, 0, s>>>(H, Hc, kWideHcap, g, z.G, wbin, wnbins, out0, nregions,
+                                                             c->wE.as<uint32_t>(), c->wHd.as<uint32_t>(), S_dev);
+        }));
+        out0 += z.nsort;
+      }
     }
+    if (nregions)
+      STCHK(launch(c, "k_sparse_apply", s, [&] {
+        sv::k_sparse_apply<<<wnbins, sv::kSpApplyThreads, (1u << wbin) / 8, s>>>(
+            c->wE.as<uint32_t>(), c->wHd.as<uint32_t>(), nregions, wbin, NB, S_dev);
+      }));
     const uint32_t nseg = (uint32_t)n;
     const uint32_t grid = l >= 13 ? nseg : (nseg + 255) / 256;
     STCHK(launch(c, "k_recount", s, [&] { sv::k_recount<<<grid, 256, 0, s>>>(S_dev, l, nseg, counts_dev); }));

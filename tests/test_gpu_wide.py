@@ -162,3 +162,26 @@ def test_wide_bound_above_2_36_sampled():
     for j in list(range(4096)) + [rng.randrange(n << l) for _ in range(3000)]:
         bit = (int(S[j >> 5]) >> (j & 31)) & 1
         assert bit == (0 if _is_probable_prime(u + 2 * j) else 1), j
+
+
+def test_wide_list_and_atomic_slices_sampled():
+    # 2^31 bits from u = 2^66 + 1 with B = 2^37 (above isqrt(v), so a bit is zero
+    # exactly when its number is prime): the slices of primes up to about 2^36.8 list
+    # their hits for the sort by table range, the later ones (fewer expected hits per
+    # workgroup) OR theirs in with atomics; sampled bits against Miller-Rabin and the
+    # counts against the table's zero bits
+    import torch
+    l, f, n = 20, 2**45, 2048
+    u, v = f * 2**(l + 1) + 1, (f + n) * 2**(l + 1)
+    B = 2**37
+    say("wide sampled l=%d f=%d n=%d B=%d" % (l, f, n, B))
+    S, c = gpu_wide(l, f, n, B)
+    rng = random.Random(66)
+    NB = n << l
+    for j in [rng.randrange(NB) for _ in range(3000)] + list(range(64)) + list(range(NB - 64, NB)):
+        bit = (int(S[j >> 5]) >> (j & 31)) & 1
+        assert bit == (0 if _is_probable_prime(u + 2 * j) else 1), j
+    ones = np.unpackbits(S.view(np.uint8)).reshape(n, -1).sum(axis=1)
+    assert np.array_equal(c.astype(np.int64), (1 << l) - ones.astype(np.int64))
+    del S, c
+    torch.cuda.empty_cache()
