@@ -54,11 +54,13 @@ def request_bytes_bound(l, n, scratch):
 class GpuExecutor:
     """Runs groups of requests with sieve_batch, one context and stream per slot.
     With single_plain, a group of one runs as the plain per-interval call (less
-    fixed cost), and so do the requests of a larger group that have sparse large
-    primes (sparse_plain), one after the other on the slot's stream before the
-    batch of the rest."""
+    fixed cost), and so do, in groups of at most split_max requests, those with
+    sparse large primes (sparse_plain), one after the other on the slot's stream
+    before the batch of the rest: that shortens a heavy request's latency, while
+    the large groups of a backlog keep their heavy requests in the batch, which
+    serves the stream faster."""
 
-    def __init__(self, primes, l, slots=3, tune=None, keep_outputs=False, single_plain=True):
+    def __init__(self, primes, l, slots=3, tune=None, keep_outputs=False, single_plain=True, split_max=4):
         import torch
         from . import api
         self.torch = torch
@@ -68,6 +70,7 @@ class GpuExecutor:
         self.tune = tune
         self.keep = keep_outputs
         self.single_plain = single_plain
+        self.split_max = split_max
         self.slots = [{"ctx": api.Context(), "stream": torch.cuda.Stream(), "busy": False} for _ in range(slots)]
         self._cost = {}
         torch.cuda.synchronize()
@@ -127,8 +130,9 @@ class GpuExecutor:
 
     def _launch(self, slot, outs):
         ctx, st = slot["ctx"], slot["stream"]
-        if self.single_plain:
-            # a group of one, and the requests with sparse large primes, as plain calls
+        if self.single_plain and len(outs) <= self.split_max:
+            # a group of one, and a small group's requests with sparse large primes,
+            # as plain calls
             one = len(outs) == 1
             for (f, n, B, S, c) in outs:
                 if one or self.sparse_plain(n, B):

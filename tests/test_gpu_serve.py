@@ -101,10 +101,12 @@ def test_admission_keeps_device_memory_within_a_binding_budget():
             g["requests"][r.rid][:2], r
 
 
-def test_group_with_sparse_request_matches_oracle():
+@pytest.mark.parametrize("split_max", [8, 0])
+def test_group_with_sparse_request_matches_oracle(split_max):
     # one group of light requests and the heavy requests 71 and 77 (sparse large
-    # primes: run as plain calls on the slot's stream before the batch of the rest),
-    # every table and count against the oracle's golden
+    # primes): run as plain calls on the slot's stream before the batch of the rest
+    # (a group within split_max), or all in the batch; every table and count against
+    # the oracle's golden
     from paper_1111_3297_amd import api, serve
     g = _serve_golden()
     l = 20
@@ -112,7 +114,7 @@ def test_group_with_sparse_request_matches_oracle():
     by = {r.rid: r for r in reqs}
     group = [by[k] for k in (70, 71, 72, 77, 78)]
     pr = api.Primes(max(r.B for r in group))
-    ex = serve.GpuExecutor(pr, l, slots=1, keep_outputs=True)
+    ex = serve.GpuExecutor(pr, l, slots=1, keep_outputs=True, split_max=split_max)
     assert [ex.sparse_plain(r.n, r.B) for r in group] == [False, True, False, True, False]
     res = ex.finish(ex.submit(group))
     for r in group:
