@@ -91,6 +91,16 @@ typedef enum {
  *               table range and OR-ed in (then the counts are taken again).  1
  *               keeps them in the buckets.  sieve_ctx_sieve and sieve_init only;
  *               batches keep every large prime in the buckets.
+ *   wide_list, wide_slot_log2, wide_sort_hits: sieve_wide only.  On tables of
+ *               at most 2^31 bits every prime above 2^32 hits at most once; a
+ *               slice of those primes either lists its hits (each workgroup in a
+ *               slot of 2^wide_slot_log2 entries, 6..13, default 12; hits beyond
+ *               it are OR-ed into S with atomics) for a sort by table range
+ *               whose workgroups gather about wide_sort_hits expected hits
+ *               (16..65536, default 7600; a workgroup takes at most 8192, any
+ *               beyond go in with atomics), or ORs every hit into S with atomics.
+ *               wide_list 0 (default): list where a slice's workgroups expect at
+ *               least 96 hits; 1: never; 2: every slice.
  */
 typedef struct {
     uint32_t tile_log2;
@@ -102,6 +112,9 @@ typedef struct {
     uint32_t wheel_log2;
     uint32_t ranges;
     uint32_t sparse;
+    uint32_t wide_list;
+    uint32_t wide_slot_log2;
+    uint32_t wide_sort_hits;
     uint32_t reserved[2];
 } sieve_tune;
 
@@ -246,13 +259,15 @@ int sieve_logsieve(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t 
  * never applies.  The primes up to min(B, 2^32 - 1) take the path of
  * sieve_ctx_sieve (the context's own table, first offsets from the 128-bit start);
  * the primes above 2^32 are produced in slices of 2^30 odd numbers by sieving
- * those numbers on the device (the context keeps one slice, 132 MiB at most), and
- * each marks its hits in S directly (fewer than one per prime on average); the
- * counts are then taken again from S.  Validity: 5 <= l <= 20, 1 <= n < 2^31,
- * n*2^l < 2^40.  Errors: SIEVE_E_ARG (null pointers, l, n), SIEVE_E_RANGE (u below
- * 2^64 or v not below 2^128), SIEVE_E_BOUND (B < 3 or B > 2^40). */
+ * those numbers on the device (the context keeps one slice, 132 MiB at most);
+ * their hits (fewer than one per prime on average) are sorted by table range and
+ * OR-ed into S a range at a time, or OR-ed into S directly (see the wide_* fields
+ * of sieve_tune; tune may be NULL); the counts are then taken again from S.
+ * Validity: 5 <= l <= 20, 1 <= n < 2^31, n*2^l < 2^40.  Errors: SIEVE_E_ARG (null
+ * pointers, l, n, a wide_* field out of range), SIEVE_E_RANGE (u below 2^64 or v
+ * not below 2^128), SIEVE_E_BOUND (B < 3 or B > 2^40). */
 int sieve_wide(sieve_ctx *ctx, uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B,
-               uint32_t *S_dev, uint32_t *counts_dev, void *stream);
+               uint32_t *S_dev, uint32_t *counts_dev, const sieve_tune *tune, void *stream);
 
 /* --- allocation-free one-shot entry point ---
  * For callers that cannot allocate device memory (code under HIP graph capture,

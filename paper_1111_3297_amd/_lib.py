@@ -41,7 +41,9 @@ class Tune(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_uint32), ("medium_log2", ctypes.c_uint32),
                 ("wave_log2", ctypes.c_uint32), ("bins_log2", ctypes.c_uint32),
                 ("groups", ctypes.c_uint32), ("bin_log2", ctypes.c_uint32), ("wheel_log2", ctypes.c_uint32),
-                ("ranges", ctypes.c_uint32), ("sparse", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("ranges", ctypes.c_uint32), ("sparse", ctypes.c_uint32), ("wide_list", ctypes.c_uint32),
+                ("wide_slot_log2", ctypes.c_uint32), ("wide_sort_hits", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class Req(ctypes.Structure):
@@ -81,7 +83,7 @@ def load():
         "sieve_ctx_trim": (i32, [vp]),
         "sieve_goldbach": (i32, [vp, vp, u32, u64, u64, vp, u64, vp, vp, vp, vp, vp]),
         "sieve_logsieve": (i32, [vp, vp, u32, u64, u64, u64, u32, vp, vp, vp, ctypes.POINTER(Tune), vp]),
-        "sieve_wide": (i32, [vp, u32, u64, u64, u64, u64, vp, vp, vp]),
+        "sieve_wide": (i32, [vp, u32, u64, u64, u64, u64, vp, vp, ctypes.POINTER(Tune), vp]),
         "sieve_primes_bytes": (i32, [vp, ctypes.POINTER(u64)]),
         "sieve_required_bound": (i32, [u32, u64, u64, ctypes.POINTER(u64)]),
         "sieve_strerror": (ctypes.c_char_p, [i32]),

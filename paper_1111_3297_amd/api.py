@@ -157,16 +157,16 @@ class Context:
                                         ctypes.c_void_p(A.data_ptr()) if A is not None else None, _tune(tune),
                                         _stream(stream)), "sieve_logsieve")
 
-    def wide(self, l, f, n, B, S, counts, stream=None):
+    def wide(self, l, f, n, B, S, counts, stream=None, tune=None):
         """Definition 1 for an interval beyond 2^64 (include/sieve.h: sieve_wide): f is
         a Python int below 2^(127-l) with f*2^l >= 2^63, B <= 2^40; S and counts as
-        for sieve()."""
+        for sieve(); tune may set the wide_* fields."""
         _require_cuda_i32(S, (n << l) // 32, "S")
         _require_cuda_i32(counts, n, "counts")
         if f < 0 or f >> 128:
             raise ValueError("f must be a non-negative integer below 2^128")
         L.check(L.load().sieve_wide(self.h, l, f & (2**64 - 1), f >> 64, n, B, ctypes.c_void_p(S.data_ptr()),
-                                    ctypes.c_void_p(counts.data_ptr()), _stream(stream)), "sieve_wide")
+                                    ctypes.c_void_p(counts.data_ptr()), _tune(tune), _stream(stream)), "sieve_wide")
 
     def sieve_scratch_bytes(self, l, f, n, B, tune=None, primes=None):
         """Device bytes a fresh context holds after sieve() of this request (planning pass)."""

@@ -1896,7 +1896,6 @@ constexpr uint64_t kSliceBits = 1ull << 30;       // odd numbers per slice
 // 3*5*7*...*47: the tile kernel reads the start of the interval only modulo the
 // pattern periods (divisors of 3*5*7*11*13 and of 17*19*23, 29*31*37, 41*43*47)
 constexpr uint64_t kProxyMod = 307444891294245705ull;
-constexpr uint32_t kWideHcap = 4096;        // hit slot of a k_wide_hits workgroup (list mode)
 constexpr double kWideListMin = 96.0;       // fewest expected hits per workgroup for the list mode
 constexpr double kWideSortHits = 7600.0;    // expected hits per sorting workgroup (sv::kSpK at most)
 
@@ -1917,10 +1916,15 @@ int check_wide(uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B,
 }  // namespace
 
 extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_hi, uint64_t n, uint64_t B,
-                          uint32_t* S_dev, uint32_t* counts_dev, void* stream) {
+                          uint32_t* S_dev, uint32_t* counts_dev, const sieve_tune* tune, void* stream) {
   if (!ctx || !S_dev || !counts_dev) return SIEVE_E_ARG;
   uint64_t W[2], NB;
   STCHK(check_wide(l, f_lo, f_hi, n, B, &W[0], &W[1], &NB));
+  const uint32_t wlist = tune ? tune->wide_list : 0u;
+  const uint32_t hcap_log = tune && tune->wide_slot_log2 ? tune->wide_slot_log2 : 12u;
+  const double sort_hits = tune && tune->wide_sort_hits ? (double)tune->wide_sort_hits : kWideSortHits;
+  if (wlist > 2 || hcap_log < 6 || hcap_log > 13 || sort_hits < 16.0 || sort_hits > 65536.0) return SIEVE_E_ARG;
+  const uint32_t hcap = 1u << hcap_log;
   Resolved R, Rs;
   STCHK(resolve_tune(l, nullptr, &R));
   STCHK(resolve_tune(kSliceLog, nullptr, &Rs));
@@ -1955,8 +1959,8 @@ extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_
       z.g = (z.nw + 256 * sv::kWideRounds - 1) / (256 * sv::kWideRounds);
       const double plo = 2.0 * (double)Fs + 1.0;
       const double e = 256.0 * sv::kWideRounds * 32.0 * (2.0 / std::log(plo)) * std::min(1.0, (double)NB / plo);
-      z.list = NB <= kLaunchBits && e >= kWideListMin;
-      z.G = z.list ? (uint32_t)std::max(1.0, std::min<double>(sv::kHsMaxG, std::floor(kWideSortHits / e))) : 0;
+      z.list = NB <= kLaunchBits && (wlist == 2 || (wlist == 0 && e >= kWideListMin));
+      z.G = z.list ? (uint32_t)std::max(1.0, std::min<double>(sv::kHsMaxG, std::floor(sort_hits / e))) : 0;
       z.nsort = z.list ? ((z.g + z.G - 1) / z.G + 7) / 8 * 8 : 0;
       nregions += z.nsort;
       if (z.list) gmax = std::max(gmax, z.g);
@@ -1969,7 +1973,7 @@ extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_
     const uint32_t wbin = sp_binlog(NB);
     const uint32_t wnbins = (uint32_t)((NB + (1ull << wbin) - 1) >> wbin);
     if (nregions) {
-      STCHK(c->wH.ensure((size_t)gmax * kWideHcap * 4));
+      STCHK(c->wH.ensure((size_t)gmax * hcap * 4));
       STCHK(c->wHc.ensure((size_t)gmax * 4 + 64));
       STCHK(c->wE.ensure((size_t)nregions * sv::kSpK * 4));
       STCHK(c->wHd.ensure((size_t)nregions * wnbins * 4 + 64));
@@ -1985,9 +1989,9 @@ extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_
       // remainder digits as wide as p < 2^(53-D) allows: 7, 8 or 11 steps
       STCHK(launch(c, "k_wide_hits", s, [&] {
         if (z.list) {
-          if (B <= (1ull << 33)) sv::k_wide_hits<20, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, kWideHcap);
-          else if (B <= (1ull << 36)) sv::k_wide_hits<17, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, kWideHcap);
-          else sv::k_wide_hits<12, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, kWideHcap);
+          if (B <= (1ull << 33)) sv::k_wide_hits<20, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, hcap);
+          else if (B <= (1ull << 36)) sv::k_wide_hits<17, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, hcap);
+          else sv::k_wide_hits<12, true><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, H, Hc, hcap);
         } else {
           if (B <= (1ull << 33)) sv::k_wide_hits<20, false><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, nullptr, nullptr, 0);
           else if (B <= (1ull << 36)) sv::k_wide_hits<17, false><<<g, 256, 0, s>>>(sl, nw, Fs, B, W[0], W[1], NB, S_dev, nullptr, nullptr, 0);
@@ -1996,7 +2000,7 @@ extern "C" int sieve_wide(sieve_ctx* ctx, uint32_t l, uint64_t f_lo, uint64_t f_
       }));
       if (z.list) {
         STCHK(launch(c, "k_hits_sort", s, [&] {
-          sv::k_hits_sort<<<z.nsort, sv::kSpThreads, 0, s>>>(H, Hc, kWideHcap, g, z.G, wbin, wnbins, out0, nregions,
+          sv::k_hits_sort<<<z.nsort, sv::kSpThreads, 0, s>>>(H, Hc, hcap, g, z.G, wbin, wnbins, out0, nregions,
                                                              c->wE.as<uint32_t>(), c->wHd.as<uint32_t>(), S_dev);
         }));
         out0 += z.nsort;

@@ -61,17 +61,24 @@ def test_argument_errors_without_gpu():
     ctx = ctypes.c_void_p()
     assert lib.sieve_ctx_create(ctypes.byref(ctx)) == 0
     M = (1 << 64) - 1
-    assert lib.sieve_wide(ctx, 12, (2**51 - 1) & M, 0, 4, 1000, dummy, dummy, None) == E["SIEVE_E_RANGE"]
+    assert lib.sieve_wide(ctx, 12, (2**51 - 1) & M, 0, 4, 1000, dummy, dummy, None, None) == E["SIEVE_E_RANGE"]
     assert lib.sieve_wide(ctx, 12, (2**115 - 4) & M, (2**115 - 4) >> 64, 4, 1000, dummy, dummy,
-                          None) == E["SIEVE_E_RANGE"]
-    assert lib.sieve_wide(ctx, 12, 0, 1 << 52, 4, 1000, dummy, dummy, None) == E["SIEVE_E_RANGE"]
-    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2**40 + 1, dummy, dummy, None) == E["SIEVE_E_BOUND"]
-    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2, dummy, dummy, None) == E["SIEVE_E_BOUND"]
-    assert lib.sieve_wide(ctx, 12, 2**51, 0, 0, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
-    assert lib.sieve_wide(ctx, 21, 2**51, 0, 4, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
-    assert lib.sieve_wide(ctx, 10, 2**53, 0, 2**30, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
-    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 1000, None, dummy, None) == E["SIEVE_E_ARG"]
-    assert lib.sieve_wide(None, 12, 2**51, 0, 4, 1000, dummy, dummy, None) == E["SIEVE_E_ARG"]
+                          None, None) == E["SIEVE_E_RANGE"]
+    assert lib.sieve_wide(ctx, 12, 0, 1 << 52, 4, 1000, dummy, dummy, None, None) == E["SIEVE_E_RANGE"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2**40 + 1, dummy, dummy, None, None) == E["SIEVE_E_BOUND"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2, dummy, dummy, None, None) == E["SIEVE_E_BOUND"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 0, 1000, dummy, dummy, None, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(ctx, 21, 2**51, 0, 4, 1000, dummy, dummy, None, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(ctx, 10, 2**53, 0, 2**30, 1000, dummy, dummy, None, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 1000, None, dummy, None, None) == E["SIEVE_E_ARG"]
+    assert lib.sieve_wide(None, 12, 2**51, 0, 4, 1000, dummy, dummy, None, None) == E["SIEVE_E_ARG"]
+    # the wide_* tuning fields: out of range is an argument error
+    for bad in ({"wide_list": 3}, {"wide_slot_log2": 5}, {"wide_slot_log2": 14}, {"wide_sort_hits": 15},
+                {"wide_sort_hits": 65537}):
+        t = _lib.Tune()
+        for k, v in bad.items():
+            setattr(t, k, v)
+        assert lib.sieve_wide(ctx, 12, 2**51, 0, 4, 2**33, dummy, dummy, ctypes.byref(t), None) == E["SIEVE_E_ARG"], bad
     assert lib.sieve_ctx_destroy(ctx) == 0
 
 

@@ -21,12 +21,12 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def gpu_wide(l, f, n, B, ctx=None):
+def gpu_wide(l, f, n, B, ctx=None, tune=None):
     import torch
     from paper_1111_3297_amd import api
     S, c = api.alloc(l, n)
     ctx = ctx or api.Context()
-    ctx.wide(l, f, n, B, S, c)
+    ctx.wide(l, f, n, B, S, c, tune=tune)
     torch.cuda.synchronize()
     ctx.check_device_errors()
     return S.cpu().numpy().view(np.uint32), c.cpu().numpy().view(np.uint32)
@@ -100,6 +100,24 @@ def test_wide_against_oracle_golden(name):
     S, c = gpu_wide(l, f, n, B)
     assert [int(x) for x in c] == g["counts"], name
     assert sha256_words(S) == g["S_sha256"], name
+
+
+@pytest.mark.parametrize("name,tune", [
+    ("wide_2p66_2g", {"wide_list": 1}),             # every hit OR-ed in with atomics
+    ("wide_2p66_2g", {"wide_slot_log2": 6}),        # 64-entry slots: most hits overflow to atomics
+    ("wide_2p66_2g", {"wide_sort_hits": 30000}),    # sorting workgroups past 8192 hits: the rest by atomics
+    ("wide_2p66", {"wide_list": 2}),                # a sparse slice listed and sorted all the same
+    ("wide_2p68", {"wide_list": 2, "wide_slot_log2": 13, "wide_sort_hits": 16}),
+])
+def test_wide_hit_paths_against_oracle_golden(name, tune):
+    # the ways a hit of a prime above 2^32 reaches the table, forced through the
+    # wide_* tuning fields: each against the oracle's golden
+    g = _golden(name)
+    l, f, n, B = g["l"], int(g["f"]), g["n"], g["B"]
+    say("wide golden %s l=%d f=%d n=%d B=%d tune=%s" % (name, l, f, n, B, tune))
+    S, c = gpu_wide(l, f, n, B, tune=tune)
+    assert [int(x) for x in c] == g["counts"], (name, tune)
+    assert sha256_words(S) == g["S_sha256"], (name, tune)
 
 
 def _is_probable_prime(N):
