@@ -138,7 +138,10 @@ typedef struct sieve_primes sieve_primes;  /* library-owned device sieving-prime
  * Generates the sieving primes on the device (Section 1.4 initialization),
  * computes the first offsets (Lemma 1), sieves each LDS tile with the pre-sieved
  * pattern of 3..13, the medium primes (Section 2.1) and the bucketed large-prime
- * hits (Sections 2.2-2.5), and writes each tile out with its popcount.
+ * hits (Sections 2.2-2.5), and writes each tile out with its popcount; large
+ * primes at least as long as a 2^31-bit launch window (one hit there at most) have
+ * their hits sorted by table range and OR-ed in after that (see sparse below), and
+ * the counts are then taken again.
  * Uses the calling thread's default context (one per device). */
 int sieve_init(uint32_t l, uint64_t f, uint64_t n, uint64_t B,
                uint32_t *S_dev, uint32_t *counts_dev, void *stream);
