@@ -84,6 +84,24 @@ def test_sparse_large_primes_direct(case):
     check_case(l, f, n, B, tune={"sparse": 1})
 
 
+def test_sparse_path_random_cases():
+    # seeded random tables whose large primes reach at least the table length, so
+    # that the sparse path runs (tables of 2^21.5..2^25 bits at starts up to 2^62,
+    # bounds from the table length to 2^28, ragged bin counts, default and small
+    # tiles), every one against the oracle
+    rng = random.Random(1111)
+    for k in range(16):
+        l = rng.choice([13, 15, 17, 18, 20])
+        nb = int(2 ** rng.uniform(21.5, 25))
+        n = max(1, nb >> l)
+        nb = n << l
+        f = rng.randrange(0, 2 ** (61 - l))
+        B = rng.randrange(nb, 2**28)
+        u, v = O.interval(l, f, n)
+        tune = {"sparse": 2} if k % 2 == 0 else {"sparse": 2, "tile_log2": 15}
+        check_case(l, f, n, B, tune=tune)
+
+
 def test_sparse_path_wide_window_golden():
     # a 2^30-bit table from 2^62 with every prime below 2^32: the sparse primes
     # (2^30 <= p < 2^32; 1.49e8 of them with 3.52e7 hits, none from those above
