@@ -265,7 +265,10 @@ int sieve_logsieve(sieve_ctx *ctx, const sieve_primes *pr, uint32_t l, uint64_t 
  * those numbers on the device (the context keeps one slice, 132 MiB at most);
  * their hits (fewer than one per prime on average) are sorted by table range and
  * OR-ed into S a range at a time, or OR-ed into S directly (see the wide_* fields
- * of sieve_tune; tune may be NULL); the counts are then taken again from S.
+ * of sieve_tune; tune may be NULL); the counts are then taken again from S.  The
+ * sort keeps one slice's hit slots (16 KiB per workgroup by default, 256 MiB) and
+ * the call's sorted hits with their bin headers (about 5 B per hit: 0.7 GB at
+ * v = 2^71 with B = 2^35) in the context as well.
  * Validity: 5 <= l <= 20, 1 <= n < 2^31, n*2^l < 2^40.  Errors: SIEVE_E_ARG (null
  * pointers, l, n, a wide_* field out of range), SIEVE_E_RANGE (u below 2^64 or v
  * not below 2^128), SIEVE_E_BOUND (B < 3 or B > 2^40). */
