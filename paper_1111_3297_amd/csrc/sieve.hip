@@ -862,7 +862,8 @@ int run_sieve(sieve_ctx* c, const sieve_primes* pr, uint32_t l, uint64_t F, uint
     const uint64_t G0 = F + ch.ls;
     if (ch.ls != cur_ls) {
       cur_ls = ch.ls;
-      const uint64_t off_ub = tab_ub;  // grid over primes >= 17
+      // grid over the primes >= 17 that k_offsets works: below the sparse ones
+      const uint64_t off_ub = sparse ? std::min<uint64_t>(tab_ub, pi_upper(sparse_lim)) : tab_ub;
       const uint32_t og = (uint32_t)((off_ub + 256 * sv::kOffPer - 1) / (256 * sv::kOffPer));
       uint32_t* off = large ? c->OFF.as<uint32_t>() : nullptr;
       if (wide) {
